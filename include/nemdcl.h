@@ -1,0 +1,161 @@
+/*
+ * nemdcl -- short-range pair forces in a deforming periodic box on AMD MI355X
+ * (gfx950), with the dynamic-size and dynamic-offset cell lists of Dobson,
+ * Fox & Saracino, "Cell List Algorithms for Nonequilibrium Molecular
+ * Dynamics" (arXiv:1412.3784).
+ *
+ * Problem (Sec. 2): a lattice with basis L = [v1 v2 v3] (columns), images
+ * q + L n of every particle, a homogeneous flow u = A x that deforms the
+ * lattice as L_t = exp(tA) L0 (Sec. 2.1), remapped by integer matrices of
+ * determinant one (Sec. 2.2).  Pairs interact through a Lennard-Jones form
+ * truncated at d_cut (zero beyond it, Sec. 3).  The library bins particles
+ * into the cells of the dynamic-size list (cells congruent to the box, Sec.
+ * 4.1) or of the dynamic-offset list (rectangular cells of the rotated box,
+ * Sec. 4.2) and sweeps each cell's neighbourhood on the GPU.
+ *
+ * Conventions for every entry point
+ *   - 3x3 matrices are row-major double[9]; a basis has the basis vectors as
+ *     its COLUMNS, so M[3*r + c] is component r of vector c.
+ *   - Positions are N x 3 row-major FP64 in DEVICE memory; forces are N x 3
+ *     row-major in DEVICE memory, FP64 for NCL_PREC_FP64 and FP32 otherwise,
+ *     in the caller's particle order.  U and W are DEVICE pointers.
+ *   - The caller owns every buffer it passes.  The handle owns its scratch
+ *     (cell arrays, sorted particle copies, partial sums), allocated by
+ *     ncl_build_cells only when N or the cell count exceeds what it holds.
+ *   - All GPU work is enqueued on the handle's stream; calls return without
+ *     waiting unless stated.  One handle per stream; handles are independent.
+ *   - Every call returns NCL_OK (0) or a negative NCL_E_* code; the text of
+ *     the last error is available from ncl_last_error.  No exceptions cross
+ *     this interface.
+ */
+#ifndef NEMDCL_H
+#define NEMDCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NCL_OK 0
+#define NCL_E_ARG (-1)           /* null pointer, bad enum, n < 0, ...            */
+#define NCL_E_BOX_TOO_SMALL (-2) /* some cell count c_i or l_i is below 1         */
+#define NCL_E_LATTICE (-3)       /* automorphism not unimodular / not diagonalised
+                                    by L0, or flow incompatible with the remap    */
+#define NCL_E_CAPACITY (-4)      /* a size exceeds a fixed limit of the library   */
+#define NCL_E_HIP (-5)           /* a HIP runtime call failed                      */
+#define NCL_E_DEVICE_FLAG (-6)   /* a kernel raised its error word (e.g. a
+                                    non-finite position); reported by the next
+                                    synchronising call                             */
+#define NCL_E_STATE (-7)         /* calls out of order (e.g. forces before cells)  */
+
+/* cell-list variant (Sec. 4.1 and 4.2) */
+#define NCL_DYNAMIC_SIZE 0
+#define NCL_DYNAMIC_OFFSET 1
+
+/* arithmetic of the pair sweep.
+ * FP64:        positions, distances, forces and sums in FP64.
+ * FP32:        FP32 offsets of each particle from its FP64 cell centre, FP32
+ *              pair maths and per-particle FP32 sums.  Pairs whose FP32 r^2
+ *              lies within a relative band of d_cut^2, and pairs closer than a
+ *              close-pair radius, are re-evaluated from FP64 positions, so the
+ *              interacting set equals the FP64 one.
+ * FP32_KAHAN:  as FP32, with Kahan-compensated per-particle sums.            */
+#define NCL_PREC_FP64 0
+#define NCL_PREC_FP32 1
+#define NCL_PREC_FP32_KAHAN 2
+
+/* options for ncl_set_option */
+#define NCL_OPT_DO_TIGHT 0       /* 1: dynamic-offset neighbourhood grown by d_cut
+                                    instead of one cell width (default 1)         */
+#define NCL_OPT_CLOSE_RADIUS 1   /* FP32 modes: pairs with r below this (in sigma)
+                                    are evaluated in FP64 (default 0.3)           */
+#define NCL_OPT_BAND 2           /* FP32 modes: relative half-width of the r^2 band
+                                    re-decided in FP64 (default 1e-5)             */
+
+typedef struct ncl_ctx *ncl_handle;
+
+typedef struct {
+    int64_t n;              /* particles binned                                   */
+    int32_t variant;        /* NCL_DYNAMIC_SIZE / NCL_DYNAMIC_OFFSET              */
+    int32_t precision;      /* NCL_PREC_*                                         */
+    int32_t cells[3];       /* c_i (Sec. 4.1) or l_i (Sec. 5.2)                   */
+    int32_t max_occupancy;  /* most particles in one cell                         */
+    int64_t ncells;
+    int64_t candidates;     /* distance checks, each ordered (i, j-image) once    */
+    int64_t pairs;          /* in-range ordered pairs: twice the interacting set  */
+    int64_t fp64_pairs;     /* FP32 modes: pairs re-evaluated in FP64             */
+    int64_t neighbourhood;  /* sum over particles of neighbourhood cells visited   */
+} ncl_stats;
+
+/* Create a handle on HIP device `device` that enqueues on `stream` (a
+ * hipStream_t owned by the caller; NULL means the default stream). */
+int ncl_create(ncl_handle *out, int device, void *stream);
+
+/* Free the handle and its scratch (synchronises its stream). */
+int ncl_destroy(ncl_handle h);
+
+/* Pair potential phi(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6] - shift for
+ * r < rc and 0 beyond (Sec. 3: forces identically zero past the cut-off);
+ * shift = phi_LJ(rc) if shift_energy != 0, else 0.  WCA (Sec. 5) is
+ * rc = 2^(1/6) sigma with shift_energy = 1.  Forces are not shifted. */
+int ncl_set_potential(ncl_handle h, double eps, double sigma, double rc, int shift_energy);
+
+int ncl_set_option(ncl_handle h, int option, double value);
+
+/* Lattice at strain time t (host pointers).  L_t = exp(tA) L0 (Sec. 2.1).
+ * naut = 0: no remap, the basis is L_t.
+ * naut = 1 (Kraynik-Reinelt, eq:kr) or 2 (generalised KR, Sec. 2.2):
+ * `aut` holds M1 (and M2) as int32[9] row-major, each of determinant 1 and
+ * such that L0 M_k L0^-1 is diagonal with positive entries exp(mu_k); A must
+ * be diagonal with t diag(A) in the span of the mu_k.  The stretch
+ * t diag(A) = sum_k alpha_k mu_k is reduced to eps = t diag(A) -
+ * sum_k p_k mu_k with p_k = floor(alpha_k + 1/2), and the basis used is
+ * Lred = exp(diag(eps)) L0 = L_t M1^-p1 M2^-p2.  Host-side FP64; no GPU work. */
+int ncl_set_lattice(ncl_handle h, const double L0[9], const double A[9], double t, int naut,
+                    const int32_t *aut);
+
+/* The basis in use and the integer matrix with Lred = L_t Mtot (host
+ * pointers; any may be NULL).  coef receives (p1, p2). */
+int ncl_get_lattice(ncl_handle h, double Lred[9], int32_t Mtot[9], int32_t coef[2]);
+
+/* Cell counts the current lattice gives for a variant: c_i = floor(h_i/d_cut)
+ * with h_i the box heights (Sec. 4.1), or l_i = floor(r_ii/d_cut) with R from
+ * the QR decomposition Lred = Q R (Sec. 4.2, 5.2).  Host only. */
+int ncl_cell_counts(ncl_handle h, int variant, int32_t counts[3]);
+
+/* Bin the n positions x (device, N x 3 FP64, any image) into the cells of
+ * `variant` for the current lattice (Sec. 4.1: every step, from the current
+ * box): wrap into the box, assign cells, counting-sort, and write the sorted
+ * copies the sweep reads (FP64 wrapped positions, FP32 offsets from the FP64
+ * cell centres, cell ids, the permutation).  Within a cell the order is by
+ * particle index, so results are run-to-run deterministic.  `x` must stay
+ * valid until ncl_compute_forces has run.  debug != 0 also keeps each
+ * particle's wrap vector for ncl_debug_pairs.  n == 0 is allowed. */
+int ncl_build_cells(ncl_handle h, int variant, const double *x, int64_t n, int precision, int debug);
+
+/* Sweep every cell's neighbourhood (27 cells, Sec. 4.1; 27/30/34/36 cells,
+ * Sec. 4.2) and write F (device, N x 3, FP64 or FP32 per precision, input
+ * order), U = sum over interacting pairs of phi (device double[1]) and
+ * W = sum over interacting pairs of r_ij (x) f_ij (device double[9],
+ * row-major, r_ij = x_i - image of x_j, f_ij the force on i from j). */
+int ncl_compute_forces(ncl_handle h, void *F, double *U, double *W);
+
+/* Per-particle pair-set digest (test aid, device int64[N] and uint64[N], input
+ * order): count_i = number of neighbour images (j, m) of i within d_cut and
+ * hash_i = sum of SplitMix64(key(j, Mtot m)) over them, m being the image in
+ * the basis Lred relative to the positions as given, so keys refer to the
+ * unreduced basis L_t.  Requires ncl_build_cells(..., debug=1). */
+int ncl_debug_pairs(ncl_handle h, int64_t *count, uint64_t *hash);
+
+/* Copy the statistics of the last build / force pass (synchronises the
+ * stream; reports NCL_E_DEVICE_FLAG if a kernel raised its error word). */
+int ncl_get_stats(ncl_handle h, ncl_stats *out);
+
+/* Text of the last error on this handle ("" if none). */
+const char *ncl_last_error(ncl_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEMDCL_H */

@@ -61,7 +61,7 @@ def _load():
     lib.orc_pairs_brute.argtypes = [P, I64, P, D, I64, P]
     lib.orc_pairs_brute.restype = I64
     lib.orc_forces_brute.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
-    lib.orc_forces_cells.argtypes = [P, I64, P, P, P, I, P, P, P, P, P, P, P]
+    lib.orc_forces_cells.argtypes = [P, I64, P, P, P, I, P, I64, P, P, P, P, P, P, P, P]
     lib.orc_max_threads.restype = I
     _lib = lib
     return lib
@@ -193,8 +193,9 @@ class Result:
     count and hash per particle (full-list view: every neighbour image of i),
     stats (candidates, directed in-range pairs) for the cell-list path."""
 
-    def __init__(self, F, u, U, W, count, hash_, stats=None):
+    def __init__(self, F, u, U, W, count, hash_, stats=None, fmag=None):
         self.F, self.u, self.U, self.W, self.count, self.hash, self.stats = F, u, U, W, count, hash_, stats
+        self.fmag = fmag  # per-particle sum of |f_ij| (cell-list path only)
 
 
 def forces_brute(x, L, pot, Mkey=None) -> Result:
@@ -215,22 +216,29 @@ def forces_brute(x, L, pot, Mkey=None) -> Result:
     return Result(F, u, float(U[0]), W, cnt, hsh)
 
 
-def forces_cells(x, L, pot, Mkey=None, threads: int = 0, want_hash: bool = True) -> Result:
-    """Forces/energy/virial via the plain dynamic-size cell list (Sec. 4.1), FP64."""
+def forces_cells(x, L, pot, Mkey=None, threads: int = 0, want_hash: bool = True, subset=None) -> Result:
+    """Forces/energy/virial via the plain dynamic-size cell list (Sec. 4.1), FP64.
+
+    subset: optional particle indices; only those are swept and the
+    per-particle outputs follow its order (U and W then cover only them)."""
     x, L = _d(x).reshape(-1, 3), _d(L).reshape(3, 3)
     n = x.shape[0]
-    F = np.zeros((n, 3))
-    u = np.zeros(n)
+    sub = None if subset is None else np.ascontiguousarray(np.asarray(subset, dtype=np.int64))
+    rows = n if sub is None else len(sub)
+    F = np.zeros((rows, 3))
+    u = np.zeros(rows)
     U = np.zeros(1)
     W = np.zeros((3, 3))
-    cnt = np.zeros(n, dtype=np.int64)
-    hsh = np.zeros(n, dtype=np.uint64) if want_hash else None
+    cnt = np.zeros(rows, dtype=np.int64)
+    hsh = np.zeros(rows, dtype=np.uint64) if want_hash else None
     st = np.zeros(2, dtype=np.int64)
+    fm = np.zeros(rows)
     Mk = None if Mkey is None else _i32(Mkey).reshape(3, 3)
-    rc = _load().orc_forces_cells(_p(x), n, _p(L), _p(pot_array(pot)), _p(Mk), int(threads), _p(F), _p(u),
-                                  _p(U), _p(W), _p(cnt), _p(hsh), _p(st))
+    rc = _load().orc_forces_cells(_p(x), n, _p(L), _p(pot_array(pot)), _p(Mk), int(threads), _p(sub),
+                                  0 if sub is None else len(sub), _p(F), _p(u), _p(U), _p(W), _p(cnt),
+                                  _p(hsh), _p(st), _p(fm))
     if rc == E_BOX_TOO_SMALL:
         raise ValueError("box too small: some c_i < 1")
     if rc != 0:
         raise ValueError(f"orc_forces_cells failed with code {rc}")
-    return Result(F, u, float(U[0]), W, cnt, hsh, (int(st[0]), int(st[1])))
+    return Result(F, u, float(U[0]), W, cnt, hsh, (int(st[0]), int(st[1])), fm)

@@ -535,8 +535,9 @@ int orc_forces_brute(const double *x, int64_t n, const double *L, const double *
 #define ORC_CHUNK 4096
 
 int orc_forces_cells(const double *x, int64_t n, const double *L, const double *pot,
-                     const int32_t *Mkey, int nthreads, double *F, double *u, double *U, double *W,
-                     int64_t *cnt, uint64_t *hash, int64_t *stats)
+                     const int32_t *Mkey, int nthreads, const int64_t *sub, int64_t nsub, double *F,
+                     double *u, double *U, double *W, int64_t *cnt, uint64_t *hash, int64_t *stats,
+                     double *fmag)
 {
     double Li[9];
     int32_t c[3];
@@ -544,12 +545,16 @@ int orc_forces_cells(const double *x, int64_t n, const double *L, const double *
     int rcode = orc_ds_counts(L, pot[2], c);
     if (rcode) return rcode;
     double rc2 = pot[2] * pot[2], shift = pot_shift(pot);
+    if (sub)
+        for (int64_t q = 0; q < nsub; ++q)
+            if (sub[q] < 0 || sub[q] >= n) return -5;
     int64_t nc = (int64_t)c[0] * c[1] * c[2];
     int64_t *img = (int64_t *)malloc(3 * n * sizeof(int64_t));
     int64_t *cell = (int64_t *)malloc(n * sizeof(int64_t));
     int64_t *start = (int64_t *)calloc(nc + 1, sizeof(int64_t));
     int64_t *members = (int64_t *)malloc(n * sizeof(int64_t));
-    int64_t nchunks = (n + ORC_CHUNK - 1) / ORC_CHUNK;
+    const int64_t nrows = sub ? nsub : n;
+    int64_t nchunks = (nrows + ORC_CHUNK - 1) / ORC_CHUNK;
     double *cU = (double *)calloc(nchunks > 0 ? nchunks : 1, sizeof(double));
     double *cW = (double *)calloc(9 * (nchunks > 0 ? nchunks : 1), sizeof(double));
     int64_t *cS = (int64_t *)calloc(2 * (nchunks > 0 ? nchunks : 1), sizeof(int64_t));
@@ -591,11 +596,12 @@ int orc_forces_cells(const double *x, int64_t n, const double *L, const double *
     for (int64_t ch = 0; ch < nchunks; ++ch) {
         double Uc = 0.0, Wc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         int64_t cand = 0, inr = 0;
-        int64_t iend = (ch + 1) * ORC_CHUNK < n ? (ch + 1) * ORC_CHUNK : n;
-        for (int64_t i = ch * ORC_CHUNK; i < iend; ++i) {
+        int64_t iend = (ch + 1) * ORC_CHUNK < nrows ? (ch + 1) * ORC_CHUNK : nrows;
+        for (int64_t row = ch * ORC_CHUNK; row < iend; ++row) {
+            const int64_t i = sub ? sub[row] : row;
             int64_t ci = cell[i];
             int64_t a[3] = {ci % c[0], (ci / c[0]) % c[1], ci / ((int64_t)c[0] * c[1])};
-            double Fi[3] = {0, 0, 0}, ui = 0.0;
+            double Fi[3] = {0, 0, 0}, ui = 0.0, mi = 0.0;
             int64_t ki = 0;
             uint64_t hi = 0;
             for (int dz = -1; dz <= 1; ++dz)
@@ -623,6 +629,7 @@ int orc_forces_cells(const double *x, int64_t n, const double *L, const double *
                             pair_eval(pot, shift, r2, &phi, &fs);
                             double rij[3] = {-d[0], -d[1], -d[2]};
                             for (int k = 0; k < 3; ++k) Fi[k] += fs * rij[k];
+                            mi += fabs(fs) * sqrt(r2);
                             ui += 0.5 * phi;
                             for (int p = 0; p < 3; ++p)
                                 for (int s = 0; s < 3; ++s) Wc[3 * p + s] += 0.5 * rij[p] * fs * rij[s];
@@ -634,10 +641,11 @@ int orc_forces_cells(const double *x, int64_t n, const double *L, const double *
                             }
                         }
                     }
-            if (F) for (int k = 0; k < 3; ++k) F[3 * i + k] = Fi[k];
-            if (u) u[i] = ui;
-            if (cnt) cnt[i] = ki;
-            if (hash) hash[i] = hi;
+            if (F) for (int k = 0; k < 3; ++k) F[3 * row + k] = Fi[k];
+            if (u) u[row] = ui;
+            if (fmag) fmag[row] = mi;
+            if (cnt) cnt[row] = ki;
+            if (hash) hash[row] = hi;
             Uc += ui;
         }
         cU[ch] = Uc;

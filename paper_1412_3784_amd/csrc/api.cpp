@@ -1,0 +1,444 @@
+// C-ABI of the nemdcl library (declared in include/nemdcl.h).
+//
+// Host side: argument checks, the FP64 lattice at time t (Sec. 2.1-2.2 of
+// Dobson, Fox & Saracino, arXiv:1412.3784), the cell geometry (Sec. 4.1,
+// 4.2), scratch management, and the kernel launches on the handle's stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/nemdcl.h"
+#include "geometry.hpp"
+#include "kernels.hpp"
+
+using namespace ncl;
+
+struct ncl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // potential
+  double eps = 1.0, sigma = 1.0, rc = 1.122462048309373, shift_on = 1.0;
+  // options
+  int do_tight = 1;
+  double close_r = 0.3, band = 1e-5;
+  // lattice
+  bool have_lattice = false;
+  RemapPolicy pol;
+  double t = 0.0;
+  double Lred[9];
+  int64_t Mtot[9];
+  int64_t coef[2] = {0, 0};
+  // build state
+  bool built = false;
+  int variant = 0, precision = 0, debug = 0;
+  uint32_t n = 0, ncells = 0;
+  const double* x = nullptr;
+  CellGeom geom;
+  // scratch
+  size_t cap_n = 0, cap_cells = 0, cap_scan = 0, cap_blocks = 0, cap_wrap = 0, cap_dbgF = 0;
+  uint32_t *cell_of = nullptr, *rank = nullptr, *count = nullptr, *cstart = nullptr, *perm = nullptr,
+           *scan_tmp = nullptr;
+  double4* pos64 = nullptr;
+  float4* pos32 = nullptr;
+  float4* pos32lo = nullptr;
+  int4* wrap = nullptr;
+  double* partial = nullptr;
+  double* dbgF = nullptr;  // internal F/U/W for ncl_debug_pairs
+  // small device words: [0..3] stats (u64), then maxocc (u32), err (i32)
+  unsigned long long* small = nullptr;
+  std::string err;
+};
+
+static int fail(ncl_ctx* h, int code, const char* fmt, const char* a = "") {
+  if (h) {
+    char buf[512];
+    snprintf(buf, sizeof buf, fmt, a);
+    h->err = buf;
+  }
+  return code;
+}
+
+static int hip_fail(ncl_ctx* h, hipError_t e, const char* where) {
+  if (h) h->err = std::string(where) + ": " + hipGetErrorString(e);
+  return NCL_E_HIP;
+}
+
+#define HIPCHK(h, call)                          \
+  do {                                           \
+    hipError_t _e = (call);                      \
+    if (_e != hipSuccess) return hip_fail(h, _e, #call); \
+  } while (0)
+
+template <class T>
+static hipError_t grow(T** p, size_t* cap, size_t need) {
+  if (*cap >= need && *p) return hipSuccess;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return e;
+    *p = nullptr;
+  }
+  size_t n = need > 0 ? need : 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e == hipSuccess) *cap = n;
+  return e;
+}
+
+extern "C" {
+
+int ncl_create(ncl_handle* out, int device, void* stream) {
+  if (!out) return NCL_E_ARG;
+  *out = nullptr;
+  ncl_ctx* h = new (std::nothrow) ncl_ctx();
+  if (!h) return NCL_E_CAPACITY;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  // no device work here: memory is allocated by the first ncl_build_cells, so
+  // the host-only calls (lattice, cell counts) work without a GPU
+  memset(h->Lred, 0, sizeof h->Lred);
+  memset(h->Mtot, 0, sizeof h->Mtot);
+  *out = h;
+  return NCL_OK;
+}
+
+int ncl_destroy(ncl_handle h) {
+  if (!h) return NCL_E_ARG;
+  int code = NCL_OK;
+  if (h->small) {  // device state exists only after a build
+    if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) code = NCL_E_HIP;
+    void* bufs[] = {h->cell_of, h->rank,    h->count,   h->cstart, h->perm, h->scan_tmp, h->pos64,
+                    h->pos32,   h->pos32lo, h->wrap, h->partial, h->dbgF, h->small};
+    for (void* b : bufs)
+      if (b && hipFree(b) != hipSuccess) code = NCL_E_HIP;
+  }
+  delete h;
+  return code;
+}
+
+int ncl_set_potential(ncl_handle h, double eps, double sigma, double rc, int shift_energy) {
+  if (!h) return NCL_E_ARG;
+  if (!(eps > 0.0) || !(sigma > 0.0) || !(rc > 0.0) || !isfinite(eps + sigma + rc))
+    return fail(h, NCL_E_ARG, "potential parameters must be positive and finite");
+  h->eps = eps;
+  h->sigma = sigma;
+  h->rc = rc;
+  h->shift_on = shift_energy ? 1.0 : 0.0;
+  h->built = false;
+  return NCL_OK;
+}
+
+int ncl_set_option(ncl_handle h, int option, double value) {
+  if (!h) return NCL_E_ARG;
+  switch (option) {
+    case NCL_OPT_DO_TIGHT: h->do_tight = value != 0.0; break;
+    case NCL_OPT_CLOSE_RADIUS:
+      if (!(value >= 0.0)) return fail(h, NCL_E_ARG, "close radius must be >= 0");
+      h->close_r = value;
+      break;
+    case NCL_OPT_BAND:
+      if (!(value >= 0.0 && value < 0.1)) return fail(h, NCL_E_ARG, "band must be in [0, 0.1)");
+      h->band = value;
+      break;
+    default: return fail(h, NCL_E_ARG, "unknown option");
+  }
+  h->built = false;
+  return NCL_OK;
+}
+
+int ncl_set_lattice(ncl_handle h, const double L0[9], const double A[9], double t, int naut, const int32_t* aut) {
+  if (!h || !L0 || !A) return NCL_E_ARG;
+  if (naut < 0 || naut > 2 || (naut > 0 && !aut)) return fail(h, NCL_E_ARG, "naut must be 0, 1 or 2 with automorphisms");
+  for (int k = 0; k < 9; ++k)
+    if (!isfinite(L0[k]) || !isfinite(A[k])) return fail(h, NCL_E_ARG, "non-finite L0 or A");
+  if (!isfinite(t)) return fail(h, NCL_E_ARG, "non-finite t");
+  RemapPolicy p;
+  int rc = remap_policy_init(&p, L0, A, naut, aut);
+  if (rc == GEOM_E_SINGULAR) return fail(h, NCL_E_LATTICE, "singular L0");
+  if (rc != GEOM_OK) return fail(h, NCL_E_LATTICE, "automorphism not unimodular / not diagonalised by L0, or flow incompatible");
+  if (naut == 0) {
+    // no remap: L_t = exp(tA) L0; closed form for diagonal A, else a Taylor
+    // series with scaling and squaring
+    bool diag = true;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        if (i != j && A[3 * i + j] != 0.0) diag = false;
+    double E[9];
+    if (diag) {
+      for (int k = 0; k < 9; ++k) E[k] = 0.0;
+      for (int i = 0; i < 3; ++i) E[4 * i] = exp(t * A[4 * i]);
+    } else {
+      double X[9], big = 0.0;
+      for (int k = 0; k < 9; ++k) {
+        X[k] = t * A[k];
+        big = fmax(big, fabs(X[k]));
+      }
+      int sq = 0;
+      while (big > 0.125 && sq < 64) {
+        big *= 0.5;
+        ++sq;
+      }
+      const double sc = ldexp(1.0, -sq);
+      for (int k = 0; k < 9; ++k) X[k] *= sc;
+      double term[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+      for (int k = 0; k < 9; ++k) E[k] = term[k];
+      for (int q = 1; q <= 24; ++q) {
+        mat_mul(term, X, term);
+        for (int k = 0; k < 9; ++k) {
+          term[k] /= (double)q;
+          E[k] += term[k];
+        }
+      }
+      for (int q = 0; q < sq; ++q) mat_mul(E, E, E);
+    }
+    mat_mul(E, L0, h->Lred);
+    h->coef[0] = h->coef[1] = 0;
+    for (int k = 0; k < 9; ++k) h->Mtot[k] = (k % 4 == 0) ? 1 : 0;
+  } else {
+    remap_at(p, t, h->Lred, h->coef);
+    remap_matrix(p, h->coef, h->Mtot);
+  }
+  h->pol = p;
+  h->t = t;
+  h->have_lattice = true;
+  h->built = false;
+  return NCL_OK;
+}
+
+int ncl_get_lattice(ncl_handle h, double Lred[9], int32_t Mtot[9], int32_t coef[2]) {
+  if (!h) return NCL_E_ARG;
+  if (!h->have_lattice) return fail(h, NCL_E_STATE, "no lattice set");
+  if (Lred)
+    for (int k = 0; k < 9; ++k) Lred[k] = h->Lred[k];
+  if (Mtot)
+    for (int k = 0; k < 9; ++k) {
+      if (h->Mtot[k] > INT32_MAX || h->Mtot[k] < INT32_MIN) return fail(h, NCL_E_CAPACITY, "Mtot overflows int32");
+      Mtot[k] = (int32_t)h->Mtot[k];
+    }
+  if (coef) {
+    coef[0] = (int32_t)h->coef[0];
+    coef[1] = (int32_t)h->coef[1];
+  }
+  return NCL_OK;
+}
+
+static int make_geom(ncl_ctx* h, int variant, CellGeom* g) {
+  int rc = cell_geom_init(g, h->Lred, h->Mtot, h->rc, variant == NCL_DYNAMIC_OFFSET ? VAR_DO : VAR_DS, h->do_tight);
+  if (rc == GEOM_E_SMALL) return fail(h, NCL_E_BOX_TOO_SMALL, "box too small for the cut-off: a cell count is below 1");
+  if (rc != GEOM_OK) return fail(h, NCL_E_LATTICE, "singular basis");
+  const double nc = (double)g->nc[0] * g->nc[1] * g->nc[2];
+  if (nc > 2147483647.0) return fail(h, NCL_E_CAPACITY, "more than 2^31-1 cells");
+  return NCL_OK;
+}
+
+int ncl_cell_counts(ncl_handle h, int variant, int32_t counts[3]) {
+  if (!h || !counts) return NCL_E_ARG;
+  if (variant != NCL_DYNAMIC_SIZE && variant != NCL_DYNAMIC_OFFSET) return fail(h, NCL_E_ARG, "bad variant");
+  if (!h->have_lattice) return fail(h, NCL_E_STATE, "no lattice set");
+  CellGeom g;
+  int rc = make_geom(h, variant, &g);
+  if (rc) return rc;
+  for (int k = 0; k < 3; ++k) counts[k] = g.nc[k];
+  return NCL_OK;
+}
+
+int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int precision, int debug) {
+  if (!h) return NCL_E_ARG;
+  if (variant != NCL_DYNAMIC_SIZE && variant != NCL_DYNAMIC_OFFSET) return fail(h, NCL_E_ARG, "bad variant");
+  if (precision < NCL_PREC_FP64 || precision > NCL_PREC_FP32_KAHAN) return fail(h, NCL_E_ARG, "bad precision");
+  if (n < 0) return fail(h, NCL_E_ARG, "n < 0");
+  if (n > 0 && !x) return fail(h, NCL_E_ARG, "null positions");
+  if (n > 0x7fffff00LL) return fail(h, NCL_E_CAPACITY, "more than 2^31 particles");
+  if (!h->have_lattice) return fail(h, NCL_E_STATE, "no lattice set");
+  HIPCHK(h, hipSetDevice(h->device));
+  if (!h->small) {
+    HIPCHK(h, hipMalloc((void**)&h->small, 8 * sizeof(unsigned long long)));
+    HIPCHK(h, hipMemsetAsync(h->small, 0, 8 * sizeof(unsigned long long), h->stream));
+  }
+  CellGeom g;
+  int rc = make_geom(h, variant, &g);
+  if (rc) return rc;
+  const uint32_t nc = (uint32_t)((uint64_t)g.nc[0] * g.nc[1] * g.nc[2]);
+  // capacity: cells never exceed V / rc^3 for a box of this volume
+  const double vcap = fabs(mat_det(h->Lred)) / (h->rc * h->rc * h->rc);
+  size_t want_cells = (size_t)nc + 1;
+  if (h->cap_cells < want_cells) {
+    const size_t bound = (size_t)fmin(vcap + 2.0, 2147483647.0);
+    want_cells = want_cells > bound ? want_cells : bound;
+  }
+  const size_t un = (size_t)n;
+  if (un > h->cap_n || !h->perm) {
+    // per-particle arrays, all sized for cap_n particles
+    void** bufs[] = {(void**)&h->cell_of, (void**)&h->rank,    (void**)&h->perm,   (void**)&h->pos64,
+                     (void**)&h->pos32,   (void**)&h->pos32lo, (void**)&h->partial};
+    for (void** b : bufs)
+      if (*b) {
+        HIPCHK(h, hipFree(*b));
+        *b = nullptr;
+      }
+    h->cap_n = 0;
+    const size_t m = un > 0 ? un : 1;
+    HIPCHK(h, hipMalloc((void**)&h->cell_of, m * sizeof(uint32_t)));
+    HIPCHK(h, hipMalloc((void**)&h->rank, m * sizeof(uint32_t)));
+    HIPCHK(h, hipMalloc((void**)&h->perm, m * sizeof(uint32_t)));
+    HIPCHK(h, hipMalloc((void**)&h->pos64, m * sizeof(double4)));
+    HIPCHK(h, hipMalloc((void**)&h->pos32, m * sizeof(float4)));
+    HIPCHK(h, hipMalloc((void**)&h->pos32lo, m * sizeof(float4)));
+    HIPCHK(h, hipMalloc((void**)&h->partial, 8 * ((m + 255) / 256 + 1) * sizeof(double)));
+    h->cap_n = m;
+  }
+  if (debug) HIPCHK(h, grow(&h->wrap, &h->cap_wrap, un));
+  if (want_cells > h->cap_cells || !h->cstart) {
+    if (h->count) HIPCHK(h, hipFree(h->count));
+    if (h->cstart) HIPCHK(h, hipFree(h->cstart));
+    h->count = h->cstart = nullptr;
+    h->cap_cells = 0;
+    HIPCHK(h, hipMalloc((void**)&h->count, want_cells * sizeof(uint32_t)));
+    HIPCHK(h, hipMalloc((void**)&h->cstart, want_cells * sizeof(uint32_t)));
+    h->cap_cells = want_cells;
+  }
+  const size_t nscan = ((size_t)nc + 2047) / 2048 + 1;
+  HIPCHK(h, grow(&h->scan_tmp, &h->cap_scan, nscan));
+
+  h->geom = g;
+  h->variant = variant;
+  h->precision = precision;
+  h->debug = debug ? 1 : 0;
+  h->n = (uint32_t)n;
+  h->ncells = nc;
+  h->x = x;
+  BuildLaunch L;
+  L.g = &h->geom;
+  L.x = x;
+  L.n = (uint32_t)n;
+  L.ncells = nc;
+  L.cell_of = h->cell_of;
+  L.rank = h->rank;
+  L.count = h->count;
+  L.cstart = h->cstart;
+  L.perm = h->perm;
+  L.scan_tmp = h->scan_tmp;
+  L.maxocc = (uint32_t*)(h->small + 4);
+  L.pos64 = h->pos64;
+  L.pos32 = h->pos32;
+  L.pos32lo = h->pos32lo;
+  L.wrap = debug ? h->wrap : nullptr;
+  L.err = (int*)(h->small + 5);
+  hipError_t e = launch_build(L, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "cell build launch");
+  h->built = true;
+  return NCL_OK;
+}
+
+static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
+  const double s2 = h->sigma * h->sigma;
+  double shift = 0.0;
+  if (h->shift_on != 0.0) {
+    const double q = s2 / (h->rc * h->rc);
+    const double q6 = q * q * q;
+    shift = 4.0 * h->eps * (q6 * q6 - q6);
+  }
+  A->pos64 = h->pos64;
+  A->pos32 = h->pos32;
+  A->pos32lo = h->pos32lo;
+  A->cstart = h->cstart;
+  A->perm = h->perm;
+  A->wrap = h->wrap;
+  A->F = F;
+  A->partial = h->partial;
+  A->stats = h->small;
+  A->dbg_count = nullptr;
+  A->dbg_hash = nullptr;
+  A->n = h->n;
+  const double rc2 = h->rc * h->rc;
+  A->rc2 = rc2;
+  A->rc2_lo = (float)(rc2 * (1.0 - h->band));
+  A->rc2_hi = (float)(rc2 * (1.0 + h->band));
+  A->rclose2 = (float)(h->close_r * h->close_r * s2);
+  A->p64.sig2 = s2;
+  A->p64.eps4 = 4.0 * h->eps;
+  A->p64.eps24 = 24.0 * h->eps;
+  A->p64.eps48 = 48.0 * h->eps;
+  A->p64.shift = shift;
+  A->p32.sig2 = (float)s2;
+  A->p32.eps4 = (float)(4.0 * h->eps);
+  A->p32.eps24 = (float)(24.0 * h->eps);
+  A->p32.eps48 = (float)(48.0 * h->eps);
+  A->p32.shift = (float)shift;
+}
+
+int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
+  if (!h) return NCL_E_ARG;
+  if (!h->built) return fail(h, NCL_E_STATE, "ncl_build_cells must precede ncl_compute_forces");
+  if (!U || !W || (h->n > 0 && !F)) return fail(h, NCL_E_ARG, "null output");
+  HIPCHK(h, hipSetDevice(h->device));
+  SweepArgs A;
+  fill_sweep_args(h, &A, F);
+  SweepLaunch L;
+  L.g = &h->geom;
+  L.args = &A;
+  L.precision = h->precision;
+  L.debug = false;
+  L.U = U;
+  L.W = W;
+  hipError_t e = launch_sweep(L, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
+  return NCL_OK;
+}
+
+int ncl_debug_pairs(ncl_handle h, int64_t* count, uint64_t* hash) {
+  if (!h) return NCL_E_ARG;
+  if (!h->built || !h->debug) return fail(h, NCL_E_STATE, "ncl_build_cells(..., debug=1) must precede ncl_debug_pairs");
+  if (h->n > 0 && (!count || !hash)) return fail(h, NCL_E_ARG, "null output");
+  HIPCHK(h, hipSetDevice(h->device));
+  HIPCHK(h, grow(&h->dbgF, &h->cap_dbgF, 3 * (size_t)h->n + 10));
+  SweepArgs A;
+  fill_sweep_args(h, &A, h->dbgF);
+  A.dbg_count = count;
+  A.dbg_hash = hash;
+  SweepLaunch L;
+  L.g = &h->geom;
+  L.args = &A;
+  L.precision = h->precision;
+  L.debug = true;
+  L.U = h->dbgF + 3 * (size_t)h->n;
+  L.W = h->dbgF + 3 * (size_t)h->n + 1;
+  hipError_t e = launch_sweep(L, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "debug sweep launch");
+  return NCL_OK;
+}
+
+int ncl_get_stats(ncl_handle h, ncl_stats* out) {
+  if (!h || !out) return NCL_E_ARG;
+  if (!h->small) return fail(h, NCL_E_STATE, "nothing built yet");
+  HIPCHK(h, hipSetDevice(h->device));
+  unsigned long long w[8];
+  HIPCHK(h, hipMemcpyAsync(w, h->small, sizeof w, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  memset(out, 0, sizeof *out);
+  out->n = h->n;
+  out->variant = h->variant;
+  out->precision = h->precision;
+  for (int k = 0; k < 3; ++k) out->cells[k] = h->geom.nc[k];
+  out->ncells = h->ncells;
+  out->candidates = (int64_t)w[0];
+  out->pairs = (int64_t)w[1];
+  out->fp64_pairs = (int64_t)w[2];
+  out->neighbourhood = (int64_t)w[3];
+  out->max_occupancy = (int32_t)(uint32_t)(w[4] & 0xffffffffull);
+  const int errw = (int)(uint32_t)(w[5] & 0xffffffffull);
+  if (errw) {
+    int zero = 0;
+    HIPCHK(h, hipMemcpyAsync((char*)(h->small + 5), &zero, sizeof zero, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return fail(h, NCL_E_DEVICE_FLAG, "a kernel flagged a non-finite position");
+  }
+  return NCL_OK;
+}
+
+const char* ncl_last_error(ncl_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

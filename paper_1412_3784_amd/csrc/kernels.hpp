@@ -1,0 +1,61 @@
+// Launch descriptors shared between the C-ABI layer and the kernel file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "geometry.hpp"
+
+namespace ncl {
+
+struct Pot32 {
+  float sig2, eps4, eps24, eps48, shift;
+};
+struct Pot64 {
+  double sig2, eps4, eps24, eps48, shift;
+};
+
+struct SweepArgs {
+  const double4* pos64;
+  const float4* pos32;
+  const float4* pos32lo;
+  const uint32_t* cstart;
+  const uint32_t* perm;
+  const int4* wrap;
+  void* F;
+  double* partial;
+  unsigned long long* stats;
+  int64_t* dbg_count;
+  uint64_t* dbg_hash;
+  uint32_t n;
+  float rc2_lo, rc2_hi, rclose2;
+  double rc2;
+  Pot32 p32;
+  Pot64 p64;
+};
+
+
+struct BuildLaunch {
+  const CellGeom* g;
+  const double* x;
+  uint32_t n, ncells;
+  uint32_t *cell_of, *rank, *count, *cstart, *perm, *scan_tmp, *maxocc;
+  double4* pos64;
+  float4* pos32;
+  float4* pos32lo;
+  int4* wrap;  // may be null
+  int* err;
+};
+
+struct SweepLaunch {
+  const CellGeom* g;
+  SweepArgs* args;
+  int precision;
+  bool debug;
+  double *U, *W;
+};
+
+hipError_t launch_build(const BuildLaunch& L, hipStream_t st);
+hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st);
+
+}  // namespace ncl
