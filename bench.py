@@ -42,6 +42,7 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 20)
     p.add_argument("--variant", default="do", choices=["do", "ds"])
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp32k", "fp64"])
+    p.add_argument("--sweep", default="particle", choices=["tiled", "particle"])
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=3, help="oracle evaluations in the CPU baseline")
     return p.parse_args()
@@ -62,6 +63,8 @@ def main():
     b0 = boxes[0]
     h = Handle(0, stream)
     h.set_potential(b0.pot)
+    from paper_1412_3784_amd import nemdcl as ncl
+    h.set_option(ncl.NCL_OPT_SWEEP, 0 if a.sweep == "tiled" else 1)
     # positions for every strain value: the fixed fractional configuration
     # carried by the flow, x_k = L(t_k) s, resident in HBM before timing
     s = torch.from_numpy(b0.frac).to(dev)
@@ -128,7 +131,7 @@ def main():
         "dtype": {"fp32": "f32 (f64 lattice)", "fp32k": "f32+kahan (f64 lattice)", "fp64": "f64"}[a.precision],
         "data": "synthetic",
         "config": {"workload": f"lj2.5_uniaxial_rho0.8_N{n}_64strains_{a.variant}", "n": n,
-                   "variant": a.variant, "precision": a.precision, "rate": 0.5, "density": 0.8, "rc": 2.5},
+                   "variant": a.variant, "precision": a.precision, "sweep": a.sweep, "rate": 0.5, "density": 0.8, "rc": 2.5},
         "breakdown_ms": {"build": 1e3 * t_build / a.steps, "force": 1e3 * t_force / a.steps},
         "candidates_per_particle": tot_cands / (a.steps * n),
         "search_efficiency": 2 * tot_pairs / tot_cands,

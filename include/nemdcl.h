@@ -56,10 +56,10 @@ extern "C" {
 /* arithmetic of the pair sweep.
  * FP64:        positions, distances, forces and sums in FP64.
  * FP32:        FP32 offsets of each particle from its FP64 cell centre, FP32
- *              pair maths and per-particle FP32 sums.  Pairs whose FP32 r^2
- *              lies within a relative band of d_cut^2, and pairs closer than a
- *              close-pair radius, are re-evaluated from FP64 positions, so the
- *              interacting set equals the FP64 one.
+ *              pair maths and per-particle FP32 sums.  Pairs whose r^2 lies
+ *              within the rounding band of d_cut^2, and pairs closer than a
+ *              close-pair radius, are re-evaluated from FP64 positions exactly
+ *              as in FP64 mode, so the interacting set equals the FP64 one.
  * FP32_KAHAN:  as FP32, with Kahan-compensated per-particle sums.            */
 #define NCL_PREC_FP64 0
 #define NCL_PREC_FP32 1
@@ -69,9 +69,11 @@ extern "C" {
 #define NCL_OPT_DO_TIGHT 0       /* 1: dynamic-offset neighbourhood grown by d_cut
                                     instead of one cell width (default 1)         */
 #define NCL_OPT_CLOSE_RADIUS 1   /* FP32 modes: pairs with r below this (in sigma)
-                                    are evaluated in FP64 (default 0.3)           */
+                                    are evaluated in FP64 (default 0.45)          */
 #define NCL_OPT_BAND 2           /* FP32 modes: relative half-width of the r^2 band
                                     re-decided in FP64 (default 1e-5)             */
+#define NCL_OPT_SWEEP 3          /* sweep kernel: 0 = LDS-tiled bricks of cells,
+                                    1 = one thread per particle (default 1)       */
 
 typedef struct ncl_ctx *ncl_handle;
 

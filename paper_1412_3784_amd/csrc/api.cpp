@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -25,7 +26,8 @@ struct ncl_ctx {
   double eps = 1.0, sigma = 1.0, rc = 1.122462048309373, shift_on = 1.0;
   // options
   int do_tight = 1;
-  double close_r = 0.3, band = 1e-5;
+  int sweep_mode = SWEEP_PARTICLE;
+  double close_r = 0.45, band = 1e-5;
   // lattice
   bool have_lattice = false;
   RemapPolicy pol;
@@ -48,6 +50,9 @@ struct ncl_ctx {
   float4* pos32lo = nullptr;
   int4* wrap = nullptr;
   double* partial = nullptr;
+  uint32_t* overflow = nullptr;
+  size_t cap_bricks = 0;
+  int brick[6] = {1, 1, 1, 1, 1, 1};  // sx, sy, sz, nbx, nby, nbz
   double* dbgF = nullptr;  // internal F/U/W for ncl_debug_pairs
   // small device words: [0..3] stats (u64), then maxocc (u32), err (i32)
   unsigned long long* small = nullptr;
@@ -110,8 +115,8 @@ int ncl_destroy(ncl_handle h) {
   int code = NCL_OK;
   if (h->small) {  // device state exists only after a build
     if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) code = NCL_E_HIP;
-    void* bufs[] = {h->cell_of, h->rank,    h->count,   h->cstart, h->perm, h->scan_tmp, h->pos64,
-                    h->pos32,   h->pos32lo, h->wrap, h->partial, h->dbgF, h->small};
+    void* bufs[] = {h->cell_of, h->rank, h->count, h->cstart, h->perm,     h->scan_tmp, h->pos64,
+                    h->pos32,   h->pos32lo, h->wrap, h->partial, h->overflow, h->dbgF, h->small};
     for (void* b : bufs)
       if (b && hipFree(b) != hipSuccess) code = NCL_E_HIP;
   }
@@ -138,6 +143,10 @@ int ncl_set_option(ncl_handle h, int option, double value) {
     case NCL_OPT_CLOSE_RADIUS:
       if (!(value >= 0.0)) return fail(h, NCL_E_ARG, "close radius must be >= 0");
       h->close_r = value;
+      break;
+    case NCL_OPT_SWEEP:
+      if (value != 0.0 && value != 1.0) return fail(h, NCL_E_ARG, "sweep mode must be 0 (tiled) or 1 (per particle)");
+      h->sweep_mode = (int)value;
       break;
     case NCL_OPT_BAND:
       if (!(value >= 0.0 && value < 0.1)) return fail(h, NCL_E_ARG, "band must be in [0, 0.1)");
@@ -245,6 +254,43 @@ int ncl_cell_counts(ncl_handle h, int variant, int32_t counts[3]) {
   return NCL_OK;
 }
 
+// Brick of home cells per workgroup of the tiled sweep: as many home
+// particles as the 256 lanes can hold while the staged neighbourhood (home
+// cells plus a rim of one or two cells, per variant) stays well inside the
+// LDS tile.  Sizes come from the mean cell occupancy.
+static void choose_brick(ncl_ctx* h, const CellGeom& g, size_t n, uint32_t nc) {
+  const double occ = nc ? (double)n / nc : 1.0;
+  // staged rim: DS adds one cell each side; DO adds the cells overlapping a
+  // band of d_cut (about 2.5-3 cells per axis with offset rows)
+  const double rim = (g.variant == VAR_DO) ? 2.6 : 2.0;
+  double best = -1e300;
+  int bs[3] = {1, 1, 1};
+  for (int sz = 1; sz <= g.nc[2] && sz <= 6; ++sz)
+    for (int sy = 1; sy <= g.nc[1] && sy <= 12; ++sy)
+      for (int sx = 1; sx <= g.nc[0] && sx <= 24; ++sx) {
+        const double home = occ * sx * sy * sz;
+        const double rows = (double)(sz + 2) * (sy + rim);
+        const double cells = rows * (sx + rim);
+        const double tile = occ * cells;
+        if (rows > 56 || cells > 800 || sy * sz > 48 || tile > 0.86 * 2240) continue;
+        const double score = fmin(home, 244.0) - 0.03 * tile;
+        if (score > best) {
+          best = score;
+          bs[0] = sx; bs[1] = sy; bs[2] = sz;
+        }
+      }
+  for (int k = 0; k < 3; ++k) {
+    h->brick[k] = bs[k];
+    h->brick[3 + k] = (g.nc[k] + bs[k] - 1) / bs[k];
+  }
+}
+
+static double ulp32(double x) {
+  x = fabs(x);
+  if (x < 1e-30) return 1e-37;
+  return ldexp(1.0, (int)floor(log2(x)) - 23);
+}
+
 int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int precision, int debug) {
   if (!h) return NCL_E_ARG;
   if (variant != NCL_DYNAMIC_SIZE && variant != NCL_DYNAMIC_OFFSET) return fail(h, NCL_E_ARG, "bad variant");
@@ -272,8 +318,8 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   const size_t un = (size_t)n;
   if (un > h->cap_n || !h->perm) {
     // per-particle arrays, all sized for cap_n particles
-    void** bufs[] = {(void**)&h->cell_of, (void**)&h->rank,    (void**)&h->perm,   (void**)&h->pos64,
-                     (void**)&h->pos32,   (void**)&h->pos32lo, (void**)&h->partial};
+    void** bufs[] = {(void**)&h->cell_of, (void**)&h->rank, (void**)&h->perm, (void**)&h->pos64,
+                     (void**)&h->pos32, (void**)&h->pos32lo};
     for (void** b : bufs)
       if (*b) {
         HIPCHK(h, hipFree(*b));
@@ -287,7 +333,6 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
     HIPCHK(h, hipMalloc((void**)&h->pos64, m * sizeof(double4)));
     HIPCHK(h, hipMalloc((void**)&h->pos32, m * sizeof(float4)));
     HIPCHK(h, hipMalloc((void**)&h->pos32lo, m * sizeof(float4)));
-    HIPCHK(h, hipMalloc((void**)&h->partial, 8 * ((m + 255) / 256 + 1) * sizeof(double)));
     h->cap_n = m;
   }
   if (debug) HIPCHK(h, grow(&h->wrap, &h->cap_wrap, un));
@@ -299,6 +344,20 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
     HIPCHK(h, hipMalloc((void**)&h->count, want_cells * sizeof(uint32_t)));
     HIPCHK(h, hipMalloc((void**)&h->cstart, want_cells * sizeof(uint32_t)));
     h->cap_cells = want_cells;
+  }
+  choose_brick(h, g, (size_t)n, nc);
+  {
+    const size_t nbr = std::max((size_t)h->brick[3] * h->brick[4] * h->brick[5], ((size_t)n + 255) / 256);
+    if (nbr + 2 > h->cap_bricks || !h->overflow) {
+      if (h->overflow) HIPCHK(h, hipFree(h->overflow));
+      if (h->partial) HIPCHK(h, hipFree(h->partial));
+      h->overflow = nullptr;
+      h->partial = nullptr;
+      h->cap_bricks = 0;
+      HIPCHK(h, hipMalloc((void**)&h->overflow, (nbr + 2) * sizeof(uint32_t)));
+      HIPCHK(h, hipMalloc((void**)&h->partial, 8 * (nbr + 2) * sizeof(double)));
+      h->cap_bricks = nbr + 2;
+    }
   }
   const size_t nscan = ((size_t)nc + 2047) / 2048 + 1;
   HIPCHK(h, grow(&h->scan_tmp, &h->cap_scan, nscan));
@@ -363,6 +422,48 @@ static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
   A->p64.eps24 = 24.0 * h->eps;
   A->p64.eps48 = 48.0 * h->eps;
   A->p64.shift = shift;
+  A->overflow = h->overflow;
+  A->sx = h->brick[0];
+  A->sy = h->brick[1];
+  A->sz = h->brick[2];
+  A->nbx = h->brick[3];
+  A->nby = h->brick[4];
+  A->nbz = h->brick[5];
+  // largest brick-frame coordinate: half the brick plus the rim of staged
+  // cells, per axis, through the cell step vectors
+  const CellGeom& g = h->geom;
+  const double ext[3] = {0.5 * A->sx + 4.0, 0.5 * A->sy + 4.0, 0.5 * A->sz + 3.0};
+  double xmax = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) s += fabs(g.cen[3 * r + c]) * ext[c];
+    xmax = fmax(xmax, s);
+  }
+  const double rc = h->rc;
+  // FP32 screening: each coordinate is off by at most half an ulp of xmax,
+  // the difference by one more half ulp; bound the r^2 error and double it
+  const double dd = ulp32(xmax) + 0.5 * ulp32(2.0 * rc);
+  const double dr2 = 2.0 * rc * sqrt(3.0) * dd + 3.0 * dd * dd + 2.0 * ulp32(rc2);
+  A->rc2c = nextafterf((float)(rc2 + 2.0 * dr2), INFINITY);
+  // residual unit: half an ulp of xmax spans 16384 units of the int16
+  A->res_unit = ulp32(xmax) / 32768.0;
+  const double dfine = A->res_unit + 4e-16 * xmax;
+  A->band64 = 4.0 * (2.0 * rc * sqrt(3.0) * dfine + 1e-15 * rc2);
+  A->rclose2_64 = h->close_r * h->close_r * s2;
+  // per-particle path: separations from FP32 offsets (at most half a cell
+  // diagonal per component) against FP64 home vectors; bound the r^2 error
+  {
+    double omax = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      double s = 0.0;
+      for (int c = 0; c < 3; ++c) s += 0.5 * fabs(g.cen[3 * r + c]);
+      omax = fmax(omax, s);
+    }
+    const double od = 0.5 * ulp32(omax) * sqrt(3.0);
+    const double er = 2.0 * rc * od + od * od + 1e-15 * rc2;
+    A->rc2_lo64 = rc2 - 4.0 * er;
+    A->rc2_hi64 = rc2 + 4.0 * er;
+  }
   A->p32.sig2 = (float)s2;
   A->p32.eps4 = (float)(4.0 * h->eps);
   A->p32.eps24 = (float)(24.0 * h->eps);
@@ -378,6 +479,7 @@ int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
   SweepArgs A;
   fill_sweep_args(h, &A, F);
   SweepLaunch L;
+  L.mode = h->sweep_mode;
   L.g = &h->geom;
   L.args = &A;
   L.precision = h->precision;
@@ -400,6 +502,7 @@ int ncl_debug_pairs(ncl_handle h, int64_t* count, uint64_t* hash) {
   A.dbg_count = count;
   A.dbg_hash = hash;
   SweepLaunch L;
+  L.mode = h->sweep_mode;
   L.g = &h->geom;
   L.args = &A;
   L.precision = h->precision;

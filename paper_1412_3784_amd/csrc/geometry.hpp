@@ -218,6 +218,7 @@ enum { VAR_DS = 0, VAR_DO = 1 };
 struct CellGeom {
   // frame: DS -> Cartesian; DO -> rotated frame x' = Q^T x
   double B[9];      // basis in the frame: DS Lred, DO R (upper triangular)
+  double Binv[9];   // B^-1
   double Finv[9];   // DS: Lred^-1 (Cartesian -> fractional); DO: Q^T
   double Q[9];      // DO: rotation (Lred = Q R); DS: identity
   double cen[9];    // DS: Lred diag(1/c) (cell step vectors as columns); DO: diag(w)
@@ -276,6 +277,7 @@ NCL_HD int cell_geom_init(CellGeom* g, const double* Lred, const int64_t* Mtot, 
     if (g->nc[0] < 1 || g->nc[1] < 1 || g->nc[2] < 1) return GEOM_E_SMALL;
     for (int k = 0; k < 9; ++k) {
       g->B[k] = Lred[k];
+      g->Binv[k] = Linv[k];
       g->Finv[k] = Linv[k];
       g->Q[k] = (k % 4 == 0) ? 1.0 : 0.0;
     }
@@ -309,6 +311,7 @@ NCL_HD int cell_geom_init(CellGeom* g, const double* Lred, const int64_t* Mtot, 
       g->w[i] = R[4 * i] / g->nc[i];
       g->cen[4 * i] = g->w[i];
     }
+    if (!mat_inv(g->B, g->Binv)) return GEOM_E_SINGULAR;
     g->grow[0] = do_tight ? rc / g->w[0] : 1.0;
     g->grow[1] = do_tight ? rc / g->w[1] : 1.0;
     for (int q = 0; q < 27; ++q) g->ds_delta[q][0] = g->ds_delta[q][1] = g->ds_delta[q][2] = 0.0;

@@ -291,13 +291,33 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
   cnt += 1;
 }
 
+// Per-lane list of in-range separations waiting for evaluation (LDS,
+// entry e of lane t at base[(e * SW_THREADS + t) * 3]); evaluated by whole
+// waves so that no lane runs the pair code alone.
+constexpr int PL_K = 16;
+constexpr int SW_THREADS_P = 256;
+struct PairList {
+  float* base;
+  int cnt;
+};
+
+template <int PREC, bool DEBUG>
+__device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PairList& L) {
+  for (int e = 0; e < L.cnt; ++e) {
+    const float* q = L.base + e * (SW_THREADS_P * 3);
+    const float dx = q[0], dy = q[1], dz = q[2];
+    pair32(acc, A.p32, dx, dy, dz, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  }
+  L.cnt = 0;
+}
+
 // Visit one neighbour cell `cj` seen through lattice image `m` (in the
 // basis Lred); `dc` is the FP64 vector from the home cell's centre to the
 // centre of that image of cj, `sh` the lattice shift B m in the frame.
 template <int PREC, bool DEBUG>
 __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
                                   uint32_t cj, bool zero_image, const double* dc, const int* m,
-                                  const double* oi, const double4& pi64, const int4& wi) {
+                                  const double* oi, const double4& pi64, const int4& wi, PairList& L) {
   const uint32_t st = A.cstart[cj], en = A.cstart[cj + 1];
   const uint32_t self = zero_image ? s : 0xffffffffu;
   acc.cand += (en - st) - ((zero_image && s >= st && s < en) ? 1u : 0u);
@@ -306,54 +326,70 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
     const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
     const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
     const double xo = pi64.x - sx, yo = pi64.y - sy, zo = pi64.z - sz;
-    for (uint32_t j = st; j < en; ++j) {
-      const double4 pj = A.pos64[j];
-      const double dx = pj.x - xo, dy = pj.y - yo, dz = pj.z - zo;
-      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-      if (r2 < A.rc2 && j != self) {
-        pair64(acc, A.p64, dx, dy, dz, r2);
-        acc.pairs += 1;
-        debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
-      }
-    }
-  } else {
-    // home position relative to the centre of this image of cj, FP64 split
-    // into FP32 hi + lo
-    const double vx = oi[0] - dc[0], vy = oi[1] - dc[1], vz = oi[2] - dc[2];
-    const float xo = (float)vx, yo = (float)vy, zo = (float)vz;
-    const float xl = (float)(vx - xo), yl = (float)(vy - yo), zl = (float)(vz - zo);
-    for (uint32_t j = st; j < en; ++j) {
-      const float4 pj = A.pos32[j];
-      float dx = pj.x - xo, dy = pj.y - yo, dz = pj.z - zo;
-      float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-      if (r2 < A.rc2_hi && j != self) {
-        if (r2 > A.rc2_lo || r2 < A.rclose2) {
-          // re-evaluate from the FP64 positions exactly as the FP64 mode does
-          const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
-          const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
-          const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
-          const double xo64 = pi64.x - sx, yo64 = pi64.y - sy, zo64 = pi64.z - sz;
-          const double4 pj64 = A.pos64[j];
-          const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
-          const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
-          acc.fp64 += 1;
-          if (e2 < A.rc2) {
-            pair64(acc, A.p64, ex, ey, ez, e2);
-            acc.pairs += 1;
-            debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
-          }
-        } else {
-          // refine the separation with the low words: d = (hi_j - hi_i) + (lo_j - lo_i)
-          const float4 pl = A.pos32lo[j];
-          dx += pl.x - xl;
-          dy += pl.y - yl;
-          dz += pl.z - zl;
-          r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-          pair32(acc, A.p32, dx, dy, dz, r2);
+    for (uint32_t j0 = st; j0 < en; j0 += 2) {
+      const double4 pa = A.pos64[j0];
+      const double4 pb = A.pos64[min(j0 + 1, en - 1)];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double4 pj = u ? pb : pa;
+        const uint32_t j = j0 + u;
+        const double dx = pj.x - xo, dy = pj.y - yo, dz = pj.z - zo;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 < A.rc2 && j < en && j != self) {
+          pair64(acc, A.p64, dx, dy, dz, r2);
           acc.pairs += 1;
           debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
         }
       }
+    }
+  } else {
+    // FP64 home position relative to the centre of this image of cj; the
+    // candidates' FP32 offsets are widened to FP64, so the separation is
+    // exact up to the rounding of the stored FP32 offsets
+    const double xo = oi[0] - dc[0], yo = oi[1] - dc[1], zo = oi[2] - dc[2];
+    // four candidate loads in flight per step (indices past the cell are
+    // clamped to its last particle and masked out)
+    for (uint32_t j0 = st; j0 < en; j0 += 4) {
+      const uint32_t jl = en - 1;
+      float4 pj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pj[u] = A.pos32[min(j0 + u, jl)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t j = j0 + u;
+        const double dx = (double)pj[u].x - xo, dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 < A.rc2_hi64 && j < en && j != self) {
+          if (DEBUG || r2 > A.rc2_lo64 || r2 < A.rclose2_64) {
+            // within the rounding band of d_cut, or a close pair: re-evaluate
+            // from the FP64 positions exactly as the FP64 mode does
+            const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
+            const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
+            const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
+            const double xo64 = pi64.x - sx, yo64 = pi64.y - sy, zo64 = pi64.z - sz;
+            const double4 pj64 = A.pos64[j];
+            const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
+            const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+            acc.fp64 += 1;
+            if (e2 < A.rc2) {
+              if (e2 < A.rclose2_64)
+                pair64(acc, A.p64, ex, ey, ez, e2);
+              else
+                pair32(acc, A.p32, (float)ex, (float)ey, (float)ez, (float)e2);
+              acc.pairs += 1;
+              debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
+            }
+          } else {
+            float* q = L.base + L.cnt * (SW_THREADS_P * 3);
+            q[0] = (float)dx;
+            q[1] = (float)dy;
+            q[2] = (float)dz;
+            L.cnt += 1;
+            acc.pairs += 1;
+          }
+        }
+      }
+      if (__ballot(L.cnt > PL_K - 5) != 0) flush_list(acc, A, L);
     }
   }
 }
@@ -364,114 +400,120 @@ __device__ inline double warp_sum(double v) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// per-particle sweep straight from global memory (used for bricks whose
+// neighbourhood does not fit the LDS tile)
+// ---------------------------------------------------------------------------
 template <int VAR, int PREC, bool DEBUG>
-__global__ void __launch_bounds__(256) k_sweep(SweepArgs A, CellGeom g) {
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t s = lb * blockDim.x + threadIdx.x;
-  const bool active = s < A.n;
-  Acc<PREC, DEBUG> acc;
-  uint32_t nbh = 0;
-  if (active) {
-    const float4 pi = A.pos32[s];
-    const double4 pi64 = A.pos64[s];
-    const int4 wi = DEBUG ? A.wrap[s] : make_int4(0, 0, 0, 0);
-    const uint32_t hc = __float_as_uint(pi.w);
-    const int a = (int)(hc % (uint32_t)g.nc[0]);
-    const int b = (int)((hc / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
-    const int c = (int)(hc / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
-    double oi[3];
-    cell_centre(g, a, b, c, oi);
-    oi[0] = pi64.x - oi[0];
-    oi[1] = pi64.y - oi[1];
-    oi[2] = pi64.z - oi[2];
-    if (VAR == VAR_DS) {
-      // 27 cells congruent to the box; the unwrapped index a + delta gives
-      // the cell (a + delta) mod c and the lattice image floor((a + delta)/c)
-      int q = 0;
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx, ++q) {
-            const int u[3] = {a + dx, b + dy, c + dz};
-            int m[3], w[3];
-            for (int k = 0; k < 3; ++k) {
-              m[k] = idiv_floor32(u[k], g.nc[k]);
-              w[k] = u[k] - m[k] * g.nc[k];
-            }
-            const uint32_t cj = (uint32_t)w[0] + (uint32_t)g.nc[0] * ((uint32_t)w[1] + (uint32_t)g.nc[1] * (uint32_t)w[2]);
-            const bool zero = (dx == 0 && dy == 0 && dz == 0);
-            visit_cell<PREC, DEBUG>(acc, A, g, s, cj, zero, g.ds_delta[q], m, oi, pi64, wi);
-            ++nbh;
+__device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s, Acc<PREC, DEBUG>& acc,
+                               uint32_t& nbh, PairList& L) {
+  const float4 pi = A.pos32[s];
+  const double4 pi64 = A.pos64[s];
+  const int4 wi = DEBUG ? A.wrap[s] : make_int4(0, 0, 0, 0);
+  const uint32_t hc = __float_as_uint(pi.w);
+  const int a = (int)(hc % (uint32_t)g.nc[0]);
+  const int b = (int)((hc / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
+  const int c = (int)(hc / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
+  double oi[3];
+  cell_centre(g, a, b, c, oi);
+  oi[0] = pi64.x - oi[0];
+  oi[1] = pi64.y - oi[1];
+  oi[2] = pi64.z - oi[2];
+  if (VAR == VAR_DS) {
+    // 27 cells congruent to the box; the unwrapped index a + delta gives
+    // the cell (a + delta) mod c and the lattice image floor((a + delta)/c)
+    int q = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx, ++q) {
+          const int u[3] = {a + dx, b + dy, c + dz};
+          int m[3], w[3];
+          for (int k = 0; k < 3; ++k) {
+            m[k] = idiv_floor32(u[k], g.nc[k]);
+            w[k] = u[k] - m[k] * g.nc[k];
           }
-    } else {
-      // rectangular cells of the rotated box; layer k (z) is offset by
-      // k r23 in y, row (j, k) by j r12 + k r13 in x
-      const double w0 = g.w[0], w1 = g.w[1], w2 = g.w[2];
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int C = c + dz;
-        const int k = idiv_floor32(C, g.nc[2]);
-        const int cz = C - k * g.nc[2];
-        const double fy = -(double)k * g.B[5] / w1;
-        const int B0 = (int)floor(b - g.grow[1] + fy);
-        const int B1 = (int)ceil(b + 1 + g.grow[1] + fy) - 1;
-        for (int Bq = B0; Bq <= B1; ++Bq) {
-          const int j = idiv_floor32(Bq, g.nc[1]);
-          const int by = Bq - j * g.nc[1];
-          const double xs = (double)j * g.B[1] + (double)k * g.B[2];
-          const double fx = -xs / w0;
-          const int A0 = (int)floor(a - g.grow[0] + fx);
-          const int A1 = (int)ceil(a + 1 + g.grow[0] + fx) - 1;
-          for (int Aq = A0; Aq <= A1; ++Aq) {
-            const int i = idiv_floor32(Aq, g.nc[0]);
-            const int ax = Aq - i * g.nc[0];
-            const uint32_t cj = (uint32_t)ax + (uint32_t)g.nc[0] * ((uint32_t)by + (uint32_t)g.nc[1] * (uint32_t)cz);
-            const int m[3] = {i, j, k};
-            // centre of this image of cj minus the home centre
-            const double dcv[3] = {(Aq - a) * w0 + xs, (Bq - b) * w1 + (double)k * g.B[5], (C - c) * w2};
-            const bool zero = (i == 0 && j == 0 && k == 0 && cj == hc);
-            visit_cell<PREC, DEBUG>(acc, A, g, s, cj, zero, dcv, m, oi, pi64, wi);
-            ++nbh;
-          }
+          const uint32_t cj = (uint32_t)w[0] + (uint32_t)g.nc[0] * ((uint32_t)w[1] + (uint32_t)g.nc[1] * (uint32_t)w[2]);
+          const bool zero = (dx == 0 && dy == 0 && dz == 0);
+          visit_cell<PREC, DEBUG>(acc, A, g, s, cj, zero, g.ds_delta[q], m, oi, pi64, wi, L);
+          ++nbh;
+        }
+  } else {
+    // rectangular cells of the rotated box; layer k (z) is offset by
+    // k r23 in y, row (j, k) by j r12 + k r13 in x
+    const double w0 = g.w[0], w1 = g.w[1], w2 = g.w[2];
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int C = c + dz;
+      const int k = idiv_floor32(C, g.nc[2]);
+      const int cz = C - k * g.nc[2];
+      const double fy = -(double)k * g.B[5] / w1;
+      const int B0 = (int)floor(b - g.grow[1] + fy);
+      const int B1 = (int)ceil(b + 1 + g.grow[1] + fy) - 1;
+      for (int Bq = B0; Bq <= B1; ++Bq) {
+        const int j = idiv_floor32(Bq, g.nc[1]);
+        const int by = Bq - j * g.nc[1];
+        const double xs = (double)j * g.B[1] + (double)k * g.B[2];
+        const double fx = -xs / w0;
+        const int A0 = (int)floor(a - g.grow[0] + fx);
+        const int A1 = (int)ceil(a + 1 + g.grow[0] + fx) - 1;
+        for (int Aq = A0; Aq <= A1; ++Aq) {
+          const int i = idiv_floor32(Aq, g.nc[0]);
+          const int ax = Aq - i * g.nc[0];
+          const uint32_t cj = (uint32_t)ax + (uint32_t)g.nc[0] * ((uint32_t)by + (uint32_t)g.nc[1] * (uint32_t)cz);
+          const int m[3] = {i, j, k};
+          const double dcv[3] = {(Aq - a) * w0 + xs, (Bq - b) * w1 + (double)k * g.B[5], (C - c) * w2};
+          const bool zero = (i == 0 && j == 0 && k == 0 && cj == hc);
+          visit_cell<PREC, DEBUG>(acc, A, g, s, cj, zero, dcv, m, oi, pi64, wi, L);
+          ++nbh;
         }
       }
     }
-    // per-particle outputs, rotated back to Cartesian for DO
-    double F[3];
-    if (PREC == 0) {
-      F[0] = acc.gx; F[1] = acc.gy; F[2] = acc.gz;
-    } else if (PREC == 2) {
-      F[0] = ((double)acc.fx - (double)acc.kx) + acc.gx;
-      F[1] = ((double)acc.fy - (double)acc.ky) + acc.gy;
-      F[2] = ((double)acc.fz - (double)acc.kz) + acc.gz;
-    } else {
-      F[0] = (double)acc.fx + acc.gx;
-      F[1] = (double)acc.fy + acc.gy;
-      F[2] = (double)acc.fz + acc.gz;
-    }
-    double Fc[3];
-    if (VAR == VAR_DO) {
-      for (int r = 0; r < 3; ++r) Fc[r] = g.Q[3 * r] * F[0] + g.Q[3 * r + 1] * F[1] + g.Q[3 * r + 2] * F[2];
-    } else {
-      Fc[0] = F[0]; Fc[1] = F[1]; Fc[2] = F[2];
-    }
-    const uint32_t io = A.perm[s];
-    if (PREC == 0) {
-      double* Fo = (double*)A.F;
-      Fo[3 * (size_t)io] = Fc[0];
-      Fo[3 * (size_t)io + 1] = Fc[1];
-      Fo[3 * (size_t)io + 2] = Fc[2];
-    } else {
-      float* Fo = (float*)A.F;
-      Fo[3 * (size_t)io] = (float)Fc[0];
-      Fo[3 * (size_t)io + 1] = (float)Fc[1];
-      Fo[3 * (size_t)io + 2] = (float)Fc[2];
-    }
-    if (DEBUG) {
-      A.dbg_count[io] = acc.dcount;
-      A.dbg_hash[io] = acc.dhash;
-    }
   }
-  // block partial sums of u and W in FP64, fixed order
-  double v[7];
+  if (PREC != 0) flush_list(acc, A, L);
+}
+
+// per-particle outputs: force rotated back to Cartesian for DO, written in
+// the caller's order; debug digest
+template <int VAR, int PREC, bool DEBUG>
+__device__ inline void write_particle(const SweepArgs& A, const CellGeom& g, uint32_t s, const Acc<PREC, DEBUG>& acc) {
+  double F[3];
+  if (PREC == 0) {
+    F[0] = acc.gx; F[1] = acc.gy; F[2] = acc.gz;
+  } else if (PREC == 2) {
+    F[0] = ((double)acc.fx - (double)acc.kx) + acc.gx;
+    F[1] = ((double)acc.fy - (double)acc.ky) + acc.gy;
+    F[2] = ((double)acc.fz - (double)acc.kz) + acc.gz;
+  } else {
+    F[0] = (double)acc.fx + acc.gx;
+    F[1] = (double)acc.fy + acc.gy;
+    F[2] = (double)acc.fz + acc.gz;
+  }
+  double Fc[3];
+  if (VAR == VAR_DO) {
+    for (int r = 0; r < 3; ++r) Fc[r] = g.Q[3 * r] * F[0] + g.Q[3 * r + 1] * F[1] + g.Q[3 * r + 2] * F[2];
+  } else {
+    Fc[0] = F[0]; Fc[1] = F[1]; Fc[2] = F[2];
+  }
+  const uint32_t io = A.perm[s];
+  if (PREC == 0) {
+    double* Fo = (double*)A.F;
+    Fo[3 * (size_t)io] = Fc[0];
+    Fo[3 * (size_t)io + 1] = Fc[1];
+    Fo[3 * (size_t)io + 2] = Fc[2];
+  } else {
+    float* Fo = (float*)A.F;
+    Fo[3 * (size_t)io] = (float)Fc[0];
+    Fo[3 * (size_t)io + 1] = (float)Fc[1];
+    Fo[3 * (size_t)io + 2] = (float)Fc[2];
+  }
+  if (DEBUG) {
+    A.dbg_count[io] = acc.dcount;
+    A.dbg_hash[io] = acc.dhash;
+  }
+}
+
+// energy and virial of one thread as FP64 (u, wxx, wyy, wzz, wxy, wxz, wyz)
+template <int PREC, bool DEBUG>
+__device__ inline void acc_energy(const Acc<PREC, DEBUG>& acc, double* v) {
   if (PREC == 0) {
     v[0] = acc.gu;
     for (int k = 0; k < 6; ++k) v[1 + k] = acc.gw[k];
@@ -479,15 +521,20 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs A, CellGeom g) {
     v[0] = (PREC == 2 ? ((double)acc.u - (double)acc.ku) : (double)acc.u) + acc.gu;
     for (int k = 0; k < 6; ++k) v[1 + k] = (double)acc.w[k];
   }
+}
+
+// block-wide FP64 sums of v[7] in a fixed order -> partial[8*slot]; integer
+// statistics added atomically.  Every thread of the block must call it.
+__device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const double* v, const uint32_t* st4) {
   __shared__ double red[4][8];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
     const double t = warp_sum(v[k]);
     if (lane == 0) red[wid][k] = t;
   }
-  // integer statistics
-  unsigned long long st[4] = {acc.cand, acc.pairs, acc.fp64, nbh};
+  unsigned long long st[4] = {st4[0], st4[1], st4[2], st4[3]};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
 #pragma unroll
@@ -501,8 +548,472 @@ __global__ void __launch_bounds__(256) k_sweep(SweepArgs A, CellGeom g) {
   __syncthreads();
   if (threadIdx.x < 7) {
     const double t = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-    A.partial[8 * (size_t)lb + threadIdx.x] = t;
+    A.partial[8 * (size_t)slot + threadIdx.x] = t;
   }
+}
+
+// ---------------------------------------------------------------------------
+// the LDS-tiled sweep
+// ---------------------------------------------------------------------------
+// One workgroup takes a brick of Sx x Sy x Sz home cells.  It stages the
+// union of the home cells' neighbourhoods (every (cell, lattice image) any
+// home cell needs) in LDS, each particle as FP32 coordinates in a frame
+// centred on the brick (image shift folded in) plus a 16-bit fixed-point
+// residual, so hi + residual carries the FP64 position to ~2^-40 of the
+// brick size.  Each lane then screens its own neighbourhood from LDS with
+// FP32 hi coordinates against a slightly widened cut-off, lists the
+// survivors, and evaluates them with a separation rebuilt in FP64 from
+// hi + residual.  Pairs whose rebuilt r^2 lies within a thin band of
+// d_cut^2 (and, in FP32 modes, pairs closer than the close-pair radius; in
+// FP64 mode, every pair) are re-evaluated from the FP64 wrapped positions
+// exactly as the FP64 per-particle path does, so every mode decides the
+// interacting set identically.
+constexpr int SW_THREADS = 256;
+constexpr int TILE_CAP = 2240;
+constexpr int LIST_K = 32;
+constexpr int MAX_LAYERS = 8;
+constexpr int MAX_ROWS = 64;
+constexpr int MAX_CELLS = 896;
+constexpr int MAX_HOME_ROWS = 48;
+constexpr int CELLS_PT = (MAX_CELLS + SW_THREADS - 1) / SW_THREADS;
+
+struct TileSmem {
+  float4 hi[TILE_CAP];          // brick-frame FP32 coordinates, .w = sorted index bits
+  uint2 res[TILE_CAP];          // int16 residuals (x | y << 16, z)
+  uint16_t list[LIST_K * SW_THREADS];
+  uint16_t cell_off[MAX_CELLS + 1];
+  uint32_t cell_g0[MAX_CELLS];  // global sorted start of each tile cell
+  uint8_t cell_row[MAX_CELLS];
+  int32_t rowA0[MAX_ROWS], rowN[MAX_ROWS], rowCell0[MAX_ROWS + 1], rowB[MAX_ROWS], rowJ[MAX_ROWS], rowL[MAX_ROWS];
+  int32_t layerRow0[MAX_LAYERS + 1], layerC[MAX_LAYERS], layerK[MAX_LAYERS], layerB0[MAX_LAYERS],
+      layerNB[MAX_LAYERS];
+  int32_t homeP0[MAX_HOME_ROWS], homeCum[MAX_HOME_ROWS + 1], homeB[MAX_HOME_ROWS], homeC[MAX_HOME_ROWS],
+      homeCell0[MAX_HOME_ROWS];
+  int32_t ntile, nrows, ncells, nhome, overflow;
+};
+
+__device__ inline int iclamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// separation of home i from image m of j exactly as the FP64 path forms it
+__device__ inline double sep64(const CellGeom& g, const double4& pi64, const double4& pj64, const int* m,
+                               double& dx, double& dy, double& dz) {
+  const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
+  const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
+  const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
+  const double xo = pi64.x - sx, yo = pi64.y - sy, zo = pi64.z - sz;
+  dx = pj64.x - xo;
+  dy = pj64.y - yo;
+  dz = pj64.z - zo;
+  return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+// inclusive scan across one wave (64 lanes)
+__device__ inline int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+template <int VAR, int PREC, bool DEBUG>
+__global__ void __launch_bounds__(SW_THREADS) k_sweep_tile(SweepArgs A, CellGeom g) {
+  __shared__ TileSmem S;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const uint32_t nbrick = (uint32_t)A.nbx * A.nby * A.nbz;
+  const uint32_t brick = xcd_block(blockIdx.x, gridDim.x);
+  if (brick >= nbrick) return;  // grid == nbrick; uniform per block
+  const int l0 = g.nc[0], l1 = g.nc[1], l2 = g.nc[2];
+  const int bxi = (int)(brick % (uint32_t)A.nbx);
+  const int byi = (int)((brick / (uint32_t)A.nbx) % (uint32_t)A.nby);
+  const int bzi = (int)(brick / ((uint32_t)A.nbx * A.nby));
+  const int a0 = bxi * A.sx, b0 = byi * A.sy, c0 = bzi * A.sz;
+  const int sx = min(A.sx, l0 - a0), sy = min(A.sy, l1 - b0), sz = min(A.sz, l2 - c0);
+  const int nlay = sz + 2;
+  // brick-frame origin: the centre of the brick, in cell-index units
+  const double uO[3] = {a0 + 0.5 * sx, b0 + 0.5 * sy, c0 + 0.5 * sz};
+  // ---- tile layout: layers (z), rows (y) per layer, cells (x) per row ----
+  if (wid == 0) {
+    int nb = 0;
+    if (lane < nlay && lane < MAX_LAYERS) {
+      const int C = c0 - 1 + lane;
+      const int kk = idiv_floor32(C, l2);
+      int B0, B1;
+      if (VAR == VAR_DS) {
+        B0 = b0 - 1;
+        B1 = b0 + sy;
+      } else {
+        const double fy = -(double)kk * g.B[5] / g.w[1];
+        B0 = (int)floor(b0 - g.grow[1] + fy);
+        B1 = (int)ceil(b0 + sy + g.grow[1] + fy) - 1;
+      }
+      nb = B1 - B0 + 1;
+      S.layerC[lane] = C;
+      S.layerK[lane] = kk;
+      S.layerB0[lane] = B0;
+      S.layerNB[lane] = nb;
+    }
+    const int inc = wave_incl_scan(nb);
+    if (lane <= nlay && lane <= MAX_LAYERS) S.layerRow0[lane] = inc - nb;
+    if (lane == 63) {
+      S.nrows = inc;
+      S.overflow = (inc > MAX_ROWS || nlay > MAX_LAYERS) ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  if (S.overflow) goto overflow;
+  // rows: x range of every row, then the prefix of cells over rows
+  if (wid == 0) {
+    int n = 0;
+    if (lane < S.nrows) {
+      const int r = lane;
+      int L = 0;
+      while (L + 1 < nlay && S.layerRow0[L + 1] <= r) ++L;
+      const int B = S.layerB0[L] + (r - S.layerRow0[L]);
+      const int j = idiv_floor32(B, l1);
+      const int kk = S.layerK[L];
+      int A0, A1;
+      if (VAR == VAR_DS) {
+        A0 = a0 - 1;
+        A1 = a0 + sx;
+      } else {
+        const double fx = -((double)j * g.B[1] + (double)kk * g.B[2]) / g.w[0];
+        A0 = (int)floor(a0 - g.grow[0] + fx);
+        A1 = (int)ceil(a0 + sx + g.grow[0] + fx) - 1;
+      }
+      n = A1 - A0 + 1;
+      S.rowA0[r] = A0;
+      S.rowN[r] = n;
+      S.rowB[r] = B;
+      S.rowJ[r] = j;
+      S.rowL[r] = L;
+    }
+    const int inc = wave_incl_scan(n);
+    if (lane < S.nrows) S.rowCell0[lane] = inc - n;
+    if (lane == 63) {
+      S.rowCell0[S.nrows] = inc;
+      S.ncells = inc;
+      if (inc > MAX_CELLS) S.overflow = 1;
+    }
+  }
+  __syncthreads();
+  if (S.overflow) goto overflow;
+  // cells: global id and particle count, CELLS_PT consecutive cells per
+  // thread, offsets by a block-wide scan
+  {
+    uint32_t cntv[CELLS_PT], sum = 0;
+#pragma unroll
+    for (int q = 0; q < CELLS_PT; ++q) {
+      const int t = tid * CELLS_PT + q;
+      cntv[q] = 0;
+      if (t < S.ncells) {
+        int lo = 0, hi = S.nrows - 1;
+        while (lo < hi) {  // last row with rowCell0 <= t
+          const int mid = (lo + hi + 1) >> 1;
+          if (S.rowCell0[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const int r = lo, L = S.rowL[r];
+        const int Aq = S.rowA0[r] + (t - S.rowCell0[r]);
+        const int i = idiv_floor32(Aq, l0);
+        const int ax = Aq - i * l0;
+        const int by = S.rowB[r] - S.rowJ[r] * l1;
+        const int cz = S.layerC[L] - S.layerK[L] * l2;
+        const uint32_t gid = (uint32_t)ax + (uint32_t)l0 * ((uint32_t)by + (uint32_t)l1 * (uint32_t)cz);
+        const uint32_t st = A.cstart[gid], en = A.cstart[gid + 1];
+        S.cell_g0[t] = st;
+        S.cell_row[t] = (uint8_t)r;
+        cntv[q] = en - st;
+        sum += en - st;
+      }
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan(sum, &total);
+#pragma unroll
+    for (int q = 0; q < CELLS_PT; ++q) {
+      const int t = tid * CELLS_PT + q;
+      if (t < S.ncells) S.cell_off[t] = (uint16_t)min(run, 65535u);
+      run += cntv[q];
+    }
+    if (tid == 0) {
+      S.cell_off[S.ncells] = (uint16_t)min(total, 65535u);
+      S.ntile = (int)min(total, 1u << 30);
+      if (total > (uint32_t)TILE_CAP) S.overflow = 1;
+    }
+  }
+  __syncthreads();
+  if (S.overflow) goto overflow;
+  // ---- stage positions, one row per wave at a time: X = (offset from own
+  //      cell centre) + (centre of the cell image) - (brick centre), kept as
+  //      FP32 hi + int16 residual in units of res_unit ----
+  {
+    const double ru_inv = 1.0 / A.res_unit;
+    for (int r = wid; r < S.nrows; r += SW_THREADS / 64) {
+      const int L = S.rowL[r];
+      const int cbeg = S.rowCell0[r], cend = S.rowCell0[r + 1];
+      const int pbeg = S.cell_off[cbeg], pend = S.cell_off[cend];
+      const int Bq = S.rowB[r], Cq = S.layerC[L];
+      const double shx = (VAR == VAR_DO) ? ((double)S.rowJ[r] * g.B[1] + (double)S.layerK[L] * g.B[2]) : 0.0;
+      const double shy = (VAR == VAR_DO) ? (double)S.layerK[L] * g.B[5] : 0.0;
+      for (int p = pbeg + lane; p < pend; p += 64) {
+        int t = cbeg;
+        while (t + 1 < cend && (int)S.cell_off[t + 1] <= p) ++t;
+        const uint32_t gj = S.cell_g0[t] + (uint32_t)(p - S.cell_off[t]);
+        const float4 h4 = A.pos32[gj];
+        const float4 l4 = A.pos32lo[gj];
+        const int Aq = S.rowA0[r] + (t - cbeg);
+        // cell-image centre minus the brick centre, from exact index offsets
+        const double du[3] = {(Aq + 0.5) - uO[0], (Bq + 0.5) - uO[1], (Cq + 0.5) - uO[2]};
+        double X[3];
+        if (VAR == VAR_DS) {
+          for (int d = 0; d < 3; ++d)
+            X[d] = g.cen[3 * d] * du[0] + g.cen[3 * d + 1] * du[1] + g.cen[3 * d + 2] * du[2];
+        } else {
+          X[0] = du[0] * g.w[0] + shx;
+          X[1] = du[1] * g.w[1] + shy;
+          X[2] = du[2] * g.w[2];
+        }
+        X[0] += (double)h4.x + (double)l4.x;
+        X[1] += (double)h4.y + (double)l4.y;
+        X[2] += (double)h4.z + (double)l4.z;
+        const float hx = (float)X[0], hy = (float)X[1], hz = (float)X[2];
+        const int rx = iclamp((int)rint((X[0] - hx) * ru_inv), -32767, 32767);
+        const int ry = iclamp((int)rint((X[1] - hy) * ru_inv), -32767, 32767);
+        const int rz = iclamp((int)rint((X[2] - hz) * ru_inv), -32767, 32767);
+        S.hi[p] = make_float4(hx, hy, hz, __uint_as_float(gj));
+        S.res[p] = make_uint2(((uint32_t)rx & 0xffffu) | ((uint32_t)ry << 16), (uint32_t)rz & 0xffffu);
+      }
+    }
+  }
+  // home rows: (b, c) rows of the brick, each a contiguous run of tile cells
+  if (wid == 0) {
+    const int nhr = sy * sz;
+    int cntr = 0;
+    if (lane < nhr && lane < MAX_HOME_ROWS) {
+      const int cc = lane / sy, bb = lane - cc * sy;
+      const int L = cc + 1;
+      const int r = S.layerRow0[L] + (b0 + bb - S.layerB0[L]);
+      const int t0 = S.rowCell0[r] + (a0 - S.rowA0[r]);
+      S.homeCell0[lane] = t0;
+      S.homeP0[lane] = S.cell_off[t0];
+      S.homeB[lane] = b0 + bb;
+      S.homeC[lane] = c0 + cc;
+      cntr = S.cell_off[t0 + sx] - S.cell_off[t0];
+    }
+    const int inc = wave_incl_scan(cntr);
+    if (lane <= nhr && lane <= MAX_HOME_ROWS) S.homeCum[lane] = inc - cntr;
+    if (lane == 63) {
+      S.nhome = inc;
+      if (nhr > MAX_HOME_ROWS) S.overflow = 1;
+    }
+  }
+  __syncthreads();
+  if (S.overflow) goto overflow;
+  {
+    const int nhr = sy * sz;
+    const float rc2c = A.rc2c;
+    const double res_unit = A.res_unit;
+    uint32_t st4[4] = {0, 0, 0, 0};
+    double v7[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int hbase = 0; hbase < S.nhome; hbase += SW_THREADS) {
+      const int h = hbase + tid;
+      const bool active = h < S.nhome;
+      Acc<PREC, DEBUG> acc;
+      if (active) {
+        int hr = 0;
+        while (hr + 1 < nhr && S.homeCum[hr + 1] <= h) ++hr;
+        const int pi = S.homeP0[hr] + (h - S.homeCum[hr]);
+        // home cell: which cell of the home row holds pi
+        int tc = S.homeCell0[hr];
+        while ((int)S.cell_off[tc + 1] <= pi) ++tc;
+        const int a = a0 + (tc - S.homeCell0[hr]);
+        const int b = S.homeB[hr], c = S.homeC[hr];
+        const float4 hi4 = S.hi[pi];
+        const uint2 rs = S.res[pi];
+        const uint32_t gi = __float_as_uint(hi4.w);
+        const double4 pi64 = A.pos64[gi];
+        const int4 wi = DEBUG ? A.wrap[gi] : make_int4(0, 0, 0, 0);
+        const double xih = hi4.x, yih = hi4.y, zih = hi4.z;
+        const double xir = (double)(int16_t)(rs.x & 0xffffu), yir = (double)(int16_t)(rs.x >> 16),
+                     zir = (double)(int16_t)(rs.y & 0xffffu);
+        const float xi = hi4.x, yi = hi4.y, zi = hi4.z;
+        // one listed candidate: separation rebuilt in FP64 from hi + residual
+        auto eval = [&](const float4& q, const uint2& qr) {
+          const double dx = ((double)q.x - xih) + ((double)(int16_t)(qr.x & 0xffffu) - xir) * res_unit;
+          const double dy = ((double)q.y - yih) + ((double)(int16_t)(qr.x >> 16) - yir) * res_unit;
+          const double dz = ((double)q.z - zih) + ((double)(int16_t)(qr.y & 0xffffu) - zir) * res_unit;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const bool band = fabs(r2 - A.rc2) <= A.band64;
+          const bool close = r2 < A.rclose2_64;
+          if (PREC == 0 || DEBUG || band || close) {
+            // exact path: recover the lattice image and re-form the
+            // separation from FP64 wrapped positions
+            const uint32_t gj = __float_as_uint(q.w);
+            const double4 pj64 = A.pos64[gj];
+            const double vx = dx - (pj64.x - pi64.x), vy = dy - (pj64.y - pi64.y), vz = dz - (pj64.z - pi64.z);
+            int m[3];
+            for (int d = 0; d < 3; ++d)
+              m[d] = (int)rint(g.Binv[3 * d] * vx + g.Binv[3 * d + 1] * vy + g.Binv[3 * d + 2] * vz);
+            double ex, ey, ez;
+            const double e2 = sep64(g, pi64, pj64, m, ex, ey, ez);
+            acc.fp64 += (PREC == 0) ? 0u : 1u;
+            if (e2 < A.rc2) {
+              if (PREC == 0 || close)
+                pair64(acc, A.p64, ex, ey, ez, e2);
+              else
+                pair32(acc, A.p32, (float)ex, (float)ey, (float)ez, (float)e2);
+              acc.pairs += 1;
+              debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, gj, m, wi);
+            }
+          } else if (r2 < A.rc2) {
+            pair32(acc, A.p32, (float)dx, (float)dy, (float)dz, (float)r2);
+            acc.pairs += 1;
+          }
+        };
+        for (int dzl = 0; dzl < 3; ++dzl) {
+          const int L = (c - c0) + dzl;
+          const int nr = S.layerNB[L] - (sy - 1);
+          const int r0 = S.layerRow0[L] + (b - b0);
+          int cnt = 0;
+          // evaluate this lane's listed candidates, two at a time
+          auto flush = [&]() {
+            int e = 0;
+            for (; e + 1 < cnt; e += 2) {
+              const int p0 = S.list[e * SW_THREADS + tid], p1 = S.list[(e + 1) * SW_THREADS + tid];
+              const float4 q0 = S.hi[p0], q1 = S.hi[p1];
+              const uint2 r0v = S.res[p0], r1v = S.res[p1];
+              if (p0 != pi) eval(q0, r0v);
+              if (p1 != pi) eval(q1, r1v);
+            }
+            if (e < cnt) {
+              const int p0 = S.list[e * SW_THREADS + tid];
+              if (p0 != pi) eval(S.hi[p0], S.res[p0]);
+            }
+            cnt = 0;
+          };
+          for (int rq = 0; rq < nr; ++rq) {
+            const int r = r0 + rq;
+            const int nc1 = S.rowN[r] - (sx - 1);
+            const int t0 = S.rowCell0[r] + (a - a0);
+            const int plo = S.cell_off[t0], phi = S.cell_off[t0 + nc1];
+            acc.cand += (uint32_t)(phi - plo);
+            st4[3] += (uint32_t)nc1;
+            // four independent LDS reads in flight per step; every
+            // candidate is written to the list slot and the count advanced
+            // only for survivors (no branch per candidate)
+            int p = plo;
+            for (; p + 4 <= phi; p += 4) {
+              const float4 q0 = S.hi[p], q1 = S.hi[p + 1], q2 = S.hi[p + 2], q3 = S.hi[p + 3];
+              float d0 = q0.x - xi, d1 = q0.y - yi, d2 = q0.z - zi;
+              const float s0 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+              d0 = q1.x - xi; d1 = q1.y - yi; d2 = q1.z - zi;
+              const float s1 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+              d0 = q2.x - xi; d1 = q2.y - yi; d2 = q2.z - zi;
+              const float s2 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+              d0 = q3.x - xi; d1 = q3.y - yi; d2 = q3.z - zi;
+              const float s3 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+              S.list[cnt * SW_THREADS + tid] = (uint16_t)p;
+              cnt += (s0 < rc2c) ? 1 : 0;
+              S.list[cnt * SW_THREADS + tid] = (uint16_t)(p + 1);
+              cnt += (s1 < rc2c) ? 1 : 0;
+              S.list[cnt * SW_THREADS + tid] = (uint16_t)(p + 2);
+              cnt += (s2 < rc2c) ? 1 : 0;
+              S.list[cnt * SW_THREADS + tid] = (uint16_t)(p + 3);
+              cnt += (s3 < rc2c) ? 1 : 0;
+              // the whole wave evaluates together as soon as one lane's list
+              // is nearly full (a lane flushing alone would idle the rest)
+              if (__ballot(cnt > LIST_K - 5) != 0) flush();
+            }
+            for (; p < phi; ++p) {
+              const float4 q0 = S.hi[p];
+              const float d0 = q0.x - xi, d1 = q0.y - yi, d2 = q0.z - zi;
+              const float s0 = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+              S.list[cnt * SW_THREADS + tid] = (uint16_t)p;
+              cnt += (s0 < rc2c) ? 1 : 0;
+            }
+            if (__ballot(cnt > LIST_K - 5) != 0) flush();
+          }
+          flush();
+        }
+        acc.cand -= 1;  // the home particle itself
+        write_particle<VAR, PREC, DEBUG>(A, g, gi, acc);
+      }
+      double v[7];
+      acc_energy(acc, v);
+      for (int kq = 0; kq < 7; ++kq) v7[kq] += v[kq];
+      st4[0] += acc.cand;
+      st4[1] += acc.pairs;
+      st4[2] += acc.fp64;
+    }
+    block_commit(A, brick, v7, st4);
+    return;
+  }
+overflow:
+  // the neighbourhood does not fit: hand the brick to the fallback kernel
+  if (tid == 0) {
+    const uint32_t q = atomicAdd(A.overflow, 1u);
+    A.overflow[1 + q] = brick;
+  }
+}
+
+// bricks listed by k_sweep_tile, one per workgroup iteration, swept per
+// particle from global memory
+template <int VAR, int PREC, bool DEBUG>
+__global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, CellGeom g) {
+  __shared__ float plist[PL_K * SW_THREADS_P * 3];
+  const uint32_t nover = A.overflow[0];
+  const int l0 = g.nc[0], l1 = g.nc[1], l2 = g.nc[2];
+  for (uint32_t q = blockIdx.x; q < nover; q += gridDim.x) {
+    const uint32_t brick = A.overflow[1 + q];
+    const int bxi = (int)(brick % (uint32_t)A.nbx);
+    const int byi = (int)((brick / (uint32_t)A.nbx) % (uint32_t)A.nby);
+    const int bzi = (int)(brick / ((uint32_t)A.nbx * A.nby));
+    const int a0 = bxi * A.sx, b0 = byi * A.sy, c0 = bzi * A.sz;
+    const int sx = min(A.sx, l0 - a0), sy = min(A.sy, l1 - b0), sz = min(A.sz, l2 - c0);
+    double v7[7] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t st4[4] = {0, 0, 0, 0};
+    for (int cc = 0; cc < sz; ++cc)
+      for (int bb = 0; bb < sy; ++bb) {
+        const uint32_t id0 = (uint32_t)a0 + (uint32_t)l0 * ((uint32_t)(b0 + bb) + (uint32_t)l1 * (uint32_t)(c0 + cc));
+        const uint32_t s0 = A.cstart[id0], s1 = A.cstart[id0 + sx];
+        for (uint32_t s = s0 + threadIdx.x; s < s1; s += SW_THREADS) {
+          Acc<PREC, DEBUG> acc;
+          uint32_t nbh = 0;
+          PairList L{plist + 3 * threadIdx.x, 0};
+          sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
+          write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
+          double v[7];
+          acc_energy(acc, v);
+          for (int k = 0; k < 7; ++k) v7[k] += v[k];
+          st4[0] += acc.cand;
+          st4[1] += acc.pairs;
+          st4[2] += acc.fp64;
+          st4[3] += nbh;
+        }
+      }
+    block_commit(A, brick, v7, st4);
+  }
+}
+
+// one thread per particle in cell order, neighbour data straight from
+// global memory (L1/L2); partial sums per workgroup
+template <int VAR, int PREC, bool DEBUG>
+__global__ void __launch_bounds__(SW_THREADS) k_sweep_particle(SweepArgs A, CellGeom g) {
+  __shared__ float plist[PL_K * SW_THREADS_P * 3];
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t s = lb * SW_THREADS + threadIdx.x;
+  Acc<PREC, DEBUG> acc;
+  uint32_t nbh = 0;
+  if (s < A.n) {
+    PairList L{plist + 3 * threadIdx.x, 0};
+    sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
+    write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
+  }
+  double v[7];
+  acc_energy(acc, v);
+  const uint32_t st4[4] = {acc.cand, acc.pairs, acc.fp64, nbh};
+  block_commit(A, lb, v, st4);
 }
 
 // U = 1/2 sum u, W = 1/2 sum w (full list counts each pair twice); DO's W is
@@ -562,26 +1073,33 @@ hipError_t launch_build(const BuildLaunch& L, hipStream_t st) {
 }
 
 template <int VAR, int PREC, bool DEBUG>
-static void sweep_t(const SweepLaunch& L, hipStream_t st, uint32_t nb) {
-  k_sweep<VAR, PREC, DEBUG><<<nb, 256, 0, st>>>(*L.args, *L.g);
+static void sweep_t(const SweepLaunch& L, hipStream_t st, uint32_t nslots) {
+  if (L.mode == SWEEP_TILED) {
+    k_sweep_tile<VAR, PREC, DEBUG><<<nslots, SW_THREADS, 0, st>>>(*L.args, *L.g);
+    k_sweep_fallback<VAR, PREC, DEBUG><<<min(nslots, 1024u), SW_THREADS, 0, st>>>(*L.args, *L.g);
+  } else {
+    k_sweep_particle<VAR, PREC, DEBUG><<<nslots, SW_THREADS, 0, st>>>(*L.args, *L.g);
+  }
 }
 
 hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
   const uint32_t n = L.args->n;
-  const uint32_t nb = n > 0 ? cdiv(n, 256) : 0;
+  const uint32_t nbrick = (L.mode == SWEEP_TILED) ? (uint32_t)L.args->nbx * L.args->nby * L.args->nbz
+                                                  : cdiv(n, SW_THREADS);
   k_fill_u32<<<1, 64, 0, st>>>((uint32_t*)L.args->stats, 8, 0u);
-  if (nb > 0) {
+  k_fill_u32<<<1, 64, 0, st>>>(L.args->overflow, 1, 0u);
+  if (n > 0 && nbrick > 0) {
     const int var = L.g->variant, prec = L.precision;
     const bool dbg = L.debug;
 #define NCL_SW(V, P)                                      \
   if (var == V && prec == P) {                            \
-    if (dbg) sweep_t<V, P, true>(L, st, nb);              \
-    else sweep_t<V, P, false>(L, st, nb);                 \
+    if (dbg) sweep_t<V, P, true>(L, st, nbrick);          \
+    else sweep_t<V, P, false>(L, st, nbrick);             \
   }
     NCL_SW(VAR_DS, 0) NCL_SW(VAR_DS, 1) NCL_SW(VAR_DS, 2)
     NCL_SW(VAR_DO, 0) NCL_SW(VAR_DO, 1) NCL_SW(VAR_DO, 2)
 #undef NCL_SW
-    k_finalize<<<1, 256, 0, st>>>(L.args->partial, nb, *L.g, L.U, L.W);
+    k_finalize<<<1, 256, 0, st>>>(L.args->partial, nbrick, *L.g, L.U, L.W);
   } else {
     k_zero_f64<<<1, 64, 0, st>>>(L.U, 1);
     k_zero_f64<<<1, 64, 0, st>>>(L.W, 9);

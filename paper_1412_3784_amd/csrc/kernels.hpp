@@ -27,9 +27,17 @@ struct SweepArgs {
   unsigned long long* stats;
   int64_t* dbg_count;
   uint64_t* dbg_hash;
+  uint32_t* overflow;      // [0] = count, then brick ids handed to the fallback
   uint32_t n;
-  float rc2_lo, rc2_hi, rclose2;
+  float rc2_lo, rc2_hi, rclose2;  // FP32 band and close radius (reported options)
+  double rc2_lo64, rc2_hi64;      // per-particle path: band around rc^2 of the mixed screen
   double rc2;
+  // LDS-tiled path: brick of sx x sy x sz home cells, nbx x nby x nbz bricks
+  int32_t sx, sy, sz, nbx, nby, nbz;
+  float rc2c;        // FP32 screening threshold: rc^2 plus the FP32 frame error bound
+  double band64;     // |r^2 - rc^2| below this is re-decided from FP64 positions
+  double res_unit;   // value of one unit of the int16 residual
+  double rclose2_64; // FP32 modes: pairs closer than this are evaluated in FP64
   Pot32 p32;
   Pot64 p64;
 };
@@ -47,7 +55,10 @@ struct BuildLaunch {
   int* err;
 };
 
+enum { SWEEP_TILED = 0, SWEEP_PARTICLE = 1 };
+
 struct SweepLaunch {
+  int mode;  // SWEEP_TILED or SWEEP_PARTICLE
   const CellGeom* g;
   SweepArgs* args;
   int precision;

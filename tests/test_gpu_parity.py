@@ -13,6 +13,8 @@ pytestmark = pytest.mark.gpu
 
 VARS = ["ds", "do"]
 PRECS = ["fp64", "fp32", "fp32k"]
+SWEEPS = [0, 1]      # LDS-tiled bricks, one thread per particle
+SWEEP_OPT = 3        # NCL_OPT_SWEEP
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -41,19 +43,21 @@ def test_tiny_boxes_all_precisions(flow, side, tf, variant):
     # the oracle's cell list is itself checked against brute force here
     b = oracle.forces_brute(x, Lr, box.pot, Mkey=oracle.reduce(box.L0, box.A, box.t, box.automorphisms)[1])
     assert (b.hash == r.hash).all()
-    for prec in PRECS:
-        g = run_gpu(box, x, variant, prec)
-        compare(g, r, prec, label=f"{flow}/{side}/{tf}/{variant}/{prec}")
+    for sweep in SWEEPS:
+        for prec in PRECS:
+            g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
+            compare(g, r, prec, label=f"{flow}/{side}/{tf}/{variant}/{prec}/sweep{sweep}")
 
 
+@pytest.mark.parametrize("sweep", SWEEPS)
 @pytest.mark.parametrize("variant", VARS)
 @pytest.mark.parametrize("prec", PRECS)
-def test_config1_wca_planar(variant, prec):
+def test_config1_wca_planar(variant, prec, sweep):
     box = wl.config1()
     x = oracle_positions(box)
     r = run_oracle(box, x)
-    g = run_gpu(box, x, variant, prec)
-    compare(g, r, prec, label=f"cfg1/{variant}/{prec}")
+    g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
+    compare(g, r, prec, label=f"cfg1/{variant}/{prec}/sweep{sweep}")
     assert g["stats"]["pairs"] == r.stats[1]
 
 
@@ -64,9 +68,10 @@ def test_config2_strain_sweep_reduced_n(k, variant):
     box = wl.config2(k=k, n=65536)
     x = oracle_positions(box)
     r = run_oracle(box, x)
-    for prec in ("fp32", "fp64"):
-        g = run_gpu(box, x, variant, prec)
-        compare(g, r, prec, label=f"cfg2/k{k}/{variant}/{prec}")
+    for sweep in SWEEPS:
+        for prec in ("fp32", "fp64"):
+            g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
+            compare(g, r, prec, label=f"cfg2/k{k}/{variant}/{prec}/sweep{sweep}")
 
 
 def test_config3_grid_jitter_reduced_n():
@@ -125,9 +130,10 @@ def test_deterministic_and_empty():
     x = oracle_positions(box)
     for variant in VARS:
         for prec in PRECS:
-            a = run_gpu(box, x, variant, prec, debug=False)
-            b = run_gpu(box, x, variant, prec, debug=False)
-            assert np.array_equal(a["F"], b["F"]) and a["U"] == b["U"] and np.array_equal(a["W"], b["W"])
+            for sweep in SWEEPS:
+                a = run_gpu(box, x, variant, prec, debug=False, options={SWEEP_OPT: sweep})
+                b = run_gpu(box, x, variant, prec, debug=False, options={SWEEP_OPT: sweep})
+                assert np.array_equal(a["F"], b["F"]) and a["U"] == b["U"] and np.array_equal(a["W"], b["W"])
     h = Handle(0)
     h.set_potential(box.pot)
     h.set_lattice(box.L0, box.A, box.t, box.automorphisms)
@@ -156,3 +162,18 @@ def test_nonfinite_position_raises_device_flag():
     # the flag is cleared once reported
     h.stats()
     h.close()
+
+
+@pytest.mark.parametrize("variant", VARS)
+def test_clustered_input_uses_fallback(variant):
+    """A dense cluster overflows the LDS tile; those bricks take the
+    per-particle path and must still match the oracle."""
+    box = wl.make_box("biaxial", 0.4, 3000, side=30.0, pot=wl.LJ25, t_frac=0.2, seed=3)
+    x = oracle_positions(box)
+    g = np.random.default_rng(9)
+    x[:1500] = x[0] + g.uniform(-2.5, 2.5, size=(1500, 3))   # ~100 particles per cell
+    r = run_oracle(box, x)
+    for sweep in SWEEPS:
+        for prec in PRECS:
+            gres = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
+            compare(gres, r, prec, label=f"cluster/{variant}/{prec}/sweep{sweep}")
