@@ -62,6 +62,7 @@ def _load():
     lib.orc_pairs_brute.restype = I64
     lib.orc_forces_brute.argtypes = [P, I64, P, P, P, P, P, P, P, P, P]
     lib.orc_forces_cells.argtypes = [P, I64, P, P, P, I, P, I64, P, P, P, P, P, P, P, P]
+    lib.orc_sllod.argtypes = [P, P, I64, P, P, D, I, P, P, D, D, I64, I, P]
     lib.orc_max_threads.restype = I
     _lib = lib
     return lib
@@ -242,3 +243,35 @@ def forces_cells(x, L, pot, Mkey=None, threads: int = 0, want_hash: bool = True,
     if rc != 0:
         raise ValueError(f"orc_forces_cells failed with code {rc}")
     return Result(F, u, float(U[0]), W, cnt, hsh, (int(st[0]), int(st[1])), fm)
+
+
+def sllod(x, p, L0, A, t0, automorphisms, pot, h, mass, nsteps, threads: int = 0):
+    """FP64 SLLOD trajectory with peculiar momenta in the deforming box (the
+    box follows the flow, Sec. 2.1; remaps by the automorphisms, Sec. 2.2),
+    symmetric splitting with the exact streaming drift; see orc_sllod.
+
+    Returns (x, p, hist): final wrapped positions and momenta, and hist of
+    shape (nsteps + 1, 8) = (t, U, W_xx, W_yy, W_zz, K_xx, K_yy, K_zz)."""
+    x = _d(x).reshape(-1, 3).copy()
+    p = _d(p).reshape(-1, 3).copy()
+    n = x.shape[0]
+    auts = list(automorphisms or [])
+    aut = _i32(np.concatenate([_i32(M).reshape(9) for M in auts])) if auts else None
+    hist = np.zeros((int(nsteps) + 1, 8))
+    rc = _load().orc_sllod(_p(x), _p(p), n, _p(_d(L0).reshape(9)), _p(_d(A).reshape(9)), float(t0), len(auts),
+                           _p(aut), _p(pot_array(pot)), float(h), float(mass), int(nsteps), int(threads), _p(hist))
+    if rc != 0:
+        raise ValueError(f"orc_sllod failed with code {rc}")
+    return x, p, hist
+
+
+def energy_balance(hist, A):
+    """H(t_n) - H(t_0) + trapezoid integral of sum_a A_aa (K_aa + W_aa): zero
+    along exact SLLOD solutions (see orc_sllod)."""
+    hist = np.asarray(hist)
+    a = np.diag(np.asarray(A, dtype=np.float64).reshape(3, 3))
+    H = 0.5 * hist[:, 5:8].sum(axis=1) + hist[:, 1]
+    rate = (a * (hist[:, 5:8] + hist[:, 2:5])).sum(axis=1)
+    dt = np.diff(hist[:, 0])
+    integ = np.concatenate([[0.0], np.cumsum(0.5 * dt * (rate[1:] + rate[:-1]))])
+    return H - H[0] + integ

@@ -667,6 +667,100 @@ int orc_forces_cells(const double *x, int64_t n, const double *L, const double *
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* SLLOD dynamics in the deforming box (Sec. 2.1: the box follows the flow,  */
+/* dL/dt = A L; particles stream with it).  The paper states the lab-frame   */
+/* equations with image momenta; this oracle uses the equivalent peculiar-   */
+/* momentum form                                                             */
+/*     dq/dt = p/m + A q,      dp/dt = F(q) - A p,                           */
+/* whose images q + L m carry the same p.  One step of length h is the       */
+/* symmetric splitting                                                       */
+/*     p <- e^{-Ah/2} p,  p <- p + (h/2) F(q),                               */
+/*     q <- e^{Ah} q + h phi1(Ah) p / m         (exact flow of dq/dt, p fixed) */
+/*     t <- t + h, F <- F(q) in the lattice at t,                            */
+/*     p <- p + (h/2) F,  p <- e^{-Ah/2} p,                                  */
+/* with phi1(z) = (e^z - 1)/z, for a diagonal A.  Positions are kept in the  */
+/* unit cell of the reduced basis (a lattice translation, Sec. 2).  Each     */
+/* record (after the start and after every step) holds                       */
+/*     t, U, W_xx, W_yy, W_zz, K_xx, K_yy, K_zz   with K_aa = sum_i p_ia^2/m,  */
+/* W as in orc_forces_cells.  Total energy H = sum_a K_aa/2 + U obeys        */
+/*     dH/dt = -sum_a A_aa (K_aa + W_aa)                                     */
+/* along exact solutions, which the tests use as a pin.                     */
+/* Returns 0, or the first failing code of orc_reduce / orc_forces_cells.   */
+/* ------------------------------------------------------------------------ */
+static double phi1(double z) { return z != 0.0 ? expm1(z) / z : 1.0; }
+
+static void wrap_into(const double *L, double *x, int64_t n)
+{
+    double Li[9];
+    if (inv3(L, Li)) return;
+    for (int64_t i = 0; i < n; ++i) {
+        double *q = x + 3 * i, f[3];
+        for (int k = 0; k < 3; ++k)
+            f[k] = floor(Li[3 * k] * q[0] + Li[3 * k + 1] * q[1] + Li[3 * k + 2] * q[2]);
+        for (int k = 0; k < 3; ++k) q[k] -= L[3 * k] * f[0] + L[3 * k + 1] * f[1] + L[3 * k + 2] * f[2];
+    }
+}
+
+static int sllod_forces(const double *x, int64_t n, const double *L0, const double *A, double t, int naut,
+                        const int32_t *aut, const double *pot, int nthreads, double *Lred, double *F,
+                        double *U, double *W)
+{
+    int32_t M[9];
+    int rc = orc_reduce(L0, A, t, naut, aut, Lred, M, NULL);
+    if (rc) return rc;
+    return orc_forces_cells(x, n, Lred, pot, NULL, nthreads, NULL, 0, F, NULL, U, W, NULL, NULL, NULL, NULL);
+}
+
+static void sllod_record(double *o, double t, double U, const double *W, const double *p, int64_t n, double m)
+{
+    double K[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) K[a] += p[3 * i + a] * p[3 * i + a] / m;
+    o[0] = t;
+    o[1] = U;
+    o[2] = W[0];
+    o[3] = W[4];
+    o[4] = W[8];
+    for (int a = 0; a < 3; ++a) o[5 + a] = K[a];
+}
+
+int orc_sllod(double *x, double *p, int64_t n, const double *L0, const double *A, double t0, int naut,
+              const int32_t *aut, const double *pot, double h, double mass, int64_t nsteps, int nthreads,
+              double *hist)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            if (r != c && A[3 * r + c] != 0.0) return -2;
+    double *F = (double *)malloc((n > 0 ? 3 * n : 1) * sizeof(double));
+    if (!F) return -4;
+    double Lred[9], U, W[9];
+    double a[3] = {A[0], A[4], A[8]};
+    double t = t0;
+    int rc = sllod_forces(x, n, L0, A, t, naut, aut, pot, nthreads, Lred, F, &U, W);
+    if (rc) { free(F); return rc; }
+    wrap_into(Lred, x, n);
+    if (hist) sllod_record(hist, t, U, W, p, n, mass);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k)
+                p[3 * i + k] = exp(-0.5 * h * a[k]) * p[3 * i + k] + 0.5 * h * F[3 * i + k];
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k)
+                x[3 * i + k] = exp(h * a[k]) * x[3 * i + k] + h * phi1(h * a[k]) * p[3 * i + k] / mass;
+        t = t0 + (double)(s + 1) * h;
+        rc = sllod_forces(x, n, L0, A, t, naut, aut, pot, nthreads, Lred, F, &U, W);
+        if (rc) { free(F); return rc; }
+        wrap_into(Lred, x, n);
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < 3; ++k)
+                p[3 * i + k] = exp(-0.5 * h * a[k]) * (p[3 * i + k] + 0.5 * h * F[3 * i + k]);
+        if (hist) sllod_record(hist + 8 * (s + 1), t, U, W, p, n, mass);
+    }
+    free(F);
+    return 0;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP
