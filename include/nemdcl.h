@@ -157,6 +157,57 @@ int ncl_get_stats(ncl_handle h, ncl_stats *out);
 /* Text of the last error on this handle ("" if none). */
 const char *ncl_last_error(ncl_handle h);
 
+/* ------------------------------------------------------------------------ */
+/* Batched form: R independent boxes ("replicas") of uneven size, each with */
+/* its own basis, diagonal traceless flow, automorphisms and strain time,   */
+/* sharing one potential and one cell-list variant.  Every kernel covers all */
+/* replicas in one launch; each replica's lattice at its current time is    */
+/* computed on the GPU in FP64 (Sec. 2.1-2.2).  Arrays are concatenated in  */
+/* replica order: positions, momenta and forces are (sum_r n_r) x 3; U is   */
+/* double[R] and W double[R*9] on the device.  Per-replica cell storage is  */
+/* sized once from floor(V_r / d_cut^3) + 1, which bounds the cell count of */
+/* both variants at any strain (Sec. 4.1 heights, Sec. 5.2 counts), so no   */
+/* call after ncl_batch_set_lattices allocates.                              */
+/* ------------------------------------------------------------------------ */
+typedef struct ncl_batch *ncl_batch_handle;
+
+/* nrep replicas of n[r] >= 1 particles (host array). */
+int ncl_batch_create(ncl_batch_handle *out, int device, void *stream, int32_t nrep, const int64_t *n);
+int ncl_batch_destroy(ncl_batch_handle b);
+/* As ncl_set_potential; call before ncl_batch_set_lattices. */
+int ncl_batch_set_potential(ncl_batch_handle b, double eps, double sigma, double rc, int shift_energy);
+/* NCL_OPT_DO_TIGHT and NCL_OPT_CLOSE_RADIUS only. */
+int ncl_batch_set_option(ncl_batch_handle b, int option, double value);
+/* Per replica r (host arrays): L0 + 9r, A + 9r (diagonal, traceless), strain
+ * time t[r], naut[r] automorphisms at aut + 18r (as in ncl_set_lattice). */
+int ncl_batch_set_lattices(ncl_batch_handle b, int variant, const double *L0, const double *A, const double *t,
+                           const int32_t *naut, const int32_t *aut);
+/* Lattices at the current times, then the cell build of every replica. */
+int ncl_batch_build_cells(ncl_batch_handle b, const double *x, int precision, int debug);
+/* Forces (FP64 or FP32 per precision), U[r], W[r*9] of every replica. */
+int ncl_batch_compute_forces(ncl_batch_handle b, void *F, double *U, double *W);
+/* Per-particle pair digest as ncl_debug_pairs, with j the index within the
+ * replica (device int64[sum n] and uint64[sum n], concatenated input order);
+ * requires debug = 1 at build. */
+int ncl_batch_debug_pairs(ncl_batch_handle b, int64_t *count, uint64_t *hash);
+/* Aggregate statistics (synchronises). */
+int ncl_batch_get_stats(ncl_batch_handle b, ncl_stats *out);
+/* Reduced bases (host double[R*9], may be NULL) and cell counts (host
+ * int32[R*3], may be NULL) in use (synchronises). */
+int ncl_batch_get_lattices(ncl_batch_handle b, double *Lred, int32_t *cells);
+/* nsteps SLLOD steps of every replica with peculiar momenta p (device,
+ * FP64): dq/dt = p/m + A q, dp/dt = F - A p, split symmetrically per step
+ * (half kick with stretch, drift, rebuild and forces, half kick), positions
+ * x (device, FP64) put back into the reduced box after every drift.  F (FP32
+ * or FP64 per the build precision), U and W hold the final forces.  With
+ * use_graph != 0 one step is captured as a HIP graph and replayed nsteps
+ * times.  hist (device, may be NULL) receives (nsteps + 1) x R records of 8
+ * doubles: t, U, W_xx, W_yy, W_zz, K_xx, K_yy, K_zz with K = sum p p^T / m.
+ * Afterwards the replicas' strain times have advanced by nsteps h. */
+int ncl_batch_sllod_run(ncl_batch_handle b, double *x, double *p, void *F, double *U, double *W, double h,
+                        double mass, int64_t nsteps, int use_graph, double *hist);
+const char *ncl_batch_last_error(ncl_batch_handle b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,6 @@ The computation lives in the HIP library libnemdcl.so (C ABI in
 include/nemdcl.h); `nemdcl` is its ctypes binding.
 """
 from . import nemdcl  # noqa: F401  (raises ImportError if the library is not built)
-from .nemdcl import Handle, NclError  # noqa: F401
+from .nemdcl import Batch, Handle, NclError  # noqa: F401
 
-__all__ = ["nemdcl", "Handle", "NclError"]
+__all__ = ["nemdcl", "Batch", "Handle", "NclError"]

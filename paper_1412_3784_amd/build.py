@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnemdcl.so")
-SOURCES = ["api.cpp", "kernels.hip"]
-HEADERS = ["geometry.hpp", "kernels.hpp"]
+SOURCES = ["api.cpp", "api_batch.cpp", "kernels.hip", "batch.hip"]
+HEADERS = ["geometry.hpp", "kernels.hpp", "batch.hpp", "sweep_common.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

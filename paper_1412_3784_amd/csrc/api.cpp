@@ -236,6 +236,7 @@ int ncl_get_lattice(ncl_handle h, double Lred[9], int32_t Mtot[9], int32_t coef[
 
 static int make_geom(ncl_ctx* h, int variant, CellGeom* g) {
   int rc = cell_geom_init(g, h->Lred, h->Mtot, h->rc, variant == NCL_DYNAMIC_OFFSET ? VAR_DO : VAR_DS, h->do_tight);
+  if (rc == GEOM_OK) cell_geom_bands(g, h->rc);
   if (rc == GEOM_E_SMALL) return fail(h, NCL_E_BOX_TOO_SMALL, "box too small for the cut-off: a cell count is below 1");
   if (rc != GEOM_OK) return fail(h, NCL_E_LATTICE, "singular basis");
   const double nc = (double)g->nc[0] * g->nc[1] * g->nc[2];
@@ -283,12 +284,6 @@ static void choose_brick(ncl_ctx* h, const CellGeom& g, size_t n, uint32_t nc) {
     h->brick[k] = bs[k];
     h->brick[3 + k] = (g.nc[k] + bs[k] - 1) / bs[k];
   }
-}
-
-static double ulp32(double x) {
-  x = fabs(x);
-  if (x < 1e-30) return 1e-37;
-  return ldexp(1.0, (int)floor(log2(x)) - 23);
 }
 
 int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int precision, int debug) {
@@ -412,6 +407,9 @@ static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
   A->dbg_count = nullptr;
   A->dbg_hash = nullptr;
   A->n = h->n;
+  A->cell0 = 0;
+  A->pad = 0;
+  A->jbase = 0;
   const double rc2 = h->rc * h->rc;
   A->rc2 = rc2;
   A->rc2_lo = (float)(rc2 * (1.0 - h->band));
@@ -450,20 +448,6 @@ static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
   const double dfine = A->res_unit + 4e-16 * xmax;
   A->band64 = 4.0 * (2.0 * rc * sqrt(3.0) * dfine + 1e-15 * rc2);
   A->rclose2_64 = h->close_r * h->close_r * s2;
-  // per-particle path: separations from FP32 offsets (at most half a cell
-  // diagonal per component) against FP64 home vectors; bound the r^2 error
-  {
-    double omax = 0.0;
-    for (int r = 0; r < 3; ++r) {
-      double s = 0.0;
-      for (int c = 0; c < 3; ++c) s += 0.5 * fabs(g.cen[3 * r + c]);
-      omax = fmax(omax, s);
-    }
-    const double od = 0.5 * ulp32(omax) * sqrt(3.0);
-    const double er = 2.0 * rc * od + od * od + 1e-15 * rc2;
-    A->rc2_lo64 = rc2 - 4.0 * er;
-    A->rc2_hi64 = rc2 + 4.0 * er;
-  }
   A->p32.sig2 = (float)s2;
   A->p32.eps4 = (float)(4.0 * h->eps);
   A->p32.eps24 = (float)(24.0 * h->eps);

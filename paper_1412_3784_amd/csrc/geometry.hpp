@@ -225,6 +225,7 @@ struct CellGeom {
   double ds_delta[27][3];  // DS: Lred diag(1/c) delta for the 27 stencil offsets
   double w[3];      // DO cell widths r_ii / l_i; DS: 1/c_i (fractional cell size)
   double grow[2];   // DO: neighbourhood growth (in cells) along x and y
+  double rc2_lo64, rc2_hi64;  // per-particle screen: rc^2 minus / plus its rounding band
   int32_t nc[3];    // cells per axis (c_i or l_i)
   int32_t variant;
   int64_t Mtot[9];  // Lred = L_t Mtot (used only for pair keys)
@@ -317,6 +318,33 @@ NCL_HD int cell_geom_init(CellGeom* g, const double* Lred, const int64_t* Mtot, 
     for (int q = 0; q < 27; ++q) g->ds_delta[q][0] = g->ds_delta[q][1] = g->ds_delta[q][2] = 0.0;
   }
   return GEOM_OK;
+}
+
+// unit in the last place of an FP32 number of magnitude |x|
+NCL_HD double ulp32(double x) {
+  x = fabs(x);
+  if (x < 1e-30) return 1e-37;
+  int e;
+  frexp(x, &e);  // x = f 2^e, f in [0.5, 1)
+  return ldexp(1.0, e - 24);
+}
+
+// Band around rc^2 for the per-particle screen: candidates carry FP32
+// offsets from their cell centre (at most half a cell diagonal per
+// component, so off by half an FP32 ulp of that), compared with an FP64 home
+// vector; r^2 within four times that error bound of rc^2 is re-decided from
+// FP64 positions.
+NCL_HD void cell_geom_bands(CellGeom* g, double rc) {
+  double omax = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) s += 0.5 * fabs(g->cen[3 * r + c]);
+    omax = fmax(omax, s);
+  }
+  const double od = 0.5 * ulp32(omax) * 1.7320508075688772;
+  const double er = 2.0 * rc * od + od * od + 1e-15 * rc * rc;
+  g->rc2_lo64 = rc * rc - 4.0 * er;
+  g->rc2_hi64 = rc * rc + 4.0 * er;
 }
 
 // ---------------------------------------------------------------------------

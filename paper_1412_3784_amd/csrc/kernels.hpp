@@ -29,8 +29,10 @@ struct SweepArgs {
   uint64_t* dbg_hash;
   uint32_t* overflow;      // [0] = count, then brick ids handed to the fallback
   uint32_t n;
+  uint32_t cell0;          // batched form: first cell of the replica in cstart
+  int32_t pad;             // batched form: slot offset added to cstart values
+  uint32_t jbase;          // batched form: first input index of the replica (pair keys are replica-local)
   float rc2_lo, rc2_hi, rclose2;  // FP32 band and close radius (reported options)
-  double rc2_lo64, rc2_hi64;      // per-particle path: band around rc^2 of the mixed screen
   double rc2;
   // LDS-tiled path: brick of sx x sy x sz home cells, nbx x nby x nbz bricks
   int32_t sx, sy, sz, nbx, nby, nbz;

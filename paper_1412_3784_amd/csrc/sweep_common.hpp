@@ -1,0 +1,415 @@
+// Device-side pieces shared by the single-box and the batched kernels: the
+// per-particle accumulators, the pair force (Sec. 3: zero past the cut-off),
+// the visit of one neighbour cell, the per-particle neighbourhood sweep of
+// both cell-list variants (Sec. 4.1, 4.2), and fixed-order reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "geometry.hpp"
+#include "kernels.hpp"
+
+namespace ncl {
+
+constexpr int SW_THREADS = 256;
+constexpr int SCAN_THREADS = 256;
+
+// blockIdx -> logical block so that each of the 8 XCDs (which receive
+// workgroups round-robin) works on one contiguous range of cells and keeps
+// its neighbour data in its own L2.
+__device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nb) {
+  const uint32_t nx = 8, per = nb / nx, rem = nb % nx;
+  const uint32_t x = bid % nx, idx = bid / nx;
+  return (x < rem) ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t wsum[SCAN_THREADS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int w = 0; w < SCAN_THREADS / 64; ++w) {
+    if (w < wid) off += wsum[w];
+    tot += wsum[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+
+// order-independent pair key hash: SplitMix64's output function (Steele, Lea
+// & Flood 2014) on (j << 32) | three 10-bit biased image components
+__device__ inline uint64_t splitmix_out(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+template <int PREC, bool DEBUG>
+struct Acc {
+  // FP32 modes: per-particle FP32 sums (+ Kahan terms), FP64 sums for the
+  // pairs taken on the FP64 path.  FP64 mode uses only the double fields.
+  float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f;
+  float kx = 0.f, ky = 0.f, kz = 0.f, ku = 0.f;
+  float w[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  double gx = 0.0, gy = 0.0, gz = 0.0, gu = 0.0;
+  double gw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  uint32_t cand = 0, pairs = 0, fp64 = 0;
+  int64_t dcount = 0;
+  uint64_t dhash = 0;
+};
+
+__device__ inline void kahan_add(float& s, float& c, float v) {
+  const float y = v - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// one FP64 pair (FP64 mode, and the FP32 modes' band / close pairs)
+template <int PREC, bool DEBUG>
+__device__ inline void pair64(Acc<PREC, DEBUG>& acc, const Pot64& p, double dx, double dy, double dz, double r2) {
+  const double r2i = 1.0 / r2;
+  const double s2 = p.sig2 * r2i;
+  const double s6 = s2 * s2 * s2;
+  const double fs = r2i * s6 * (p.eps48 * s6 - p.eps24);
+  const double phi = s6 * (p.eps4 * s6 - p.eps4) - p.shift;
+  acc.gx -= fs * dx;
+  acc.gy -= fs * dy;
+  acc.gz -= fs * dz;
+  acc.gu += phi;
+  if (PREC == 0) {
+    acc.gw[0] += fs * dx * dx;
+    acc.gw[1] += fs * dy * dy;
+    acc.gw[2] += fs * dz * dz;
+    acc.gw[3] += fs * dx * dy;
+    acc.gw[4] += fs * dx * dz;
+    acc.gw[5] += fs * dy * dz;
+  } else {
+    acc.w[0] += (float)(fs * dx * dx);
+    acc.w[1] += (float)(fs * dy * dy);
+    acc.w[2] += (float)(fs * dz * dz);
+    acc.w[3] += (float)(fs * dx * dy);
+    acc.w[4] += (float)(fs * dx * dz);
+    acc.w[5] += (float)(fs * dy * dz);
+  }
+}
+
+template <int PREC, bool DEBUG>
+__device__ inline void pair32(Acc<PREC, DEBUG>& acc, const Pot32& p, float dx, float dy, float dz, float r2) {
+  const float r2i = __builtin_amdgcn_rcpf(r2);
+  const float s2 = p.sig2 * r2i;
+  const float s6 = s2 * s2 * s2;
+  const float fs = r2i * s6 * fmaf(p.eps48, s6, -p.eps24);
+  const float phi = fmaf(s6, fmaf(p.eps4, s6, -p.eps4), -p.shift);
+  if (PREC == 2) {
+    kahan_add(acc.fx, acc.kx, -fs * dx);
+    kahan_add(acc.fy, acc.ky, -fs * dy);
+    kahan_add(acc.fz, acc.kz, -fs * dz);
+    kahan_add(acc.u, acc.ku, phi);
+  } else {
+    acc.fx = fmaf(-fs, dx, acc.fx);
+    acc.fy = fmaf(-fs, dy, acc.fy);
+    acc.fz = fmaf(-fs, dz, acc.fz);
+    acc.u += phi;
+  }
+  const float fdx = fs * dx, fdy = fs * dy;
+  acc.w[0] = fmaf(fdx, dx, acc.w[0]);
+  acc.w[1] = fmaf(fdy, dy, acc.w[1]);
+  acc.w[2] = fmaf(fs * dz, dz, acc.w[2]);
+  acc.w[3] = fmaf(fdx, dy, acc.w[3]);
+  acc.w[4] = fmaf(fdx, dz, acc.w[4]);
+  acc.w[5] = fmaf(fdy, dz, acc.w[5]);
+}
+
+template <bool DEBUG>
+__device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& A, const CellGeom& g, uint32_t j,
+                                  const int* mcell, const int4& wi) {
+  if (!DEBUG) return;
+  const int4 wj = A.wrap[j];
+  // image relative to the positions as given: x_j + Lred m - x_i
+  const int64_t m[3] = {(int64_t)mcell[0] - wj.x + wi.x, (int64_t)mcell[1] - wj.y + wi.y,
+                        (int64_t)mcell[2] - wj.z + wi.z};
+  int64_t mk[3];
+  for (int r = 0; r < 3; ++r) mk[r] = g.Mtot[3 * r] * m[0] + g.Mtot[3 * r + 1] * m[1] + g.Mtot[3 * r + 2] * m[2];
+  uint64_t key = ((uint64_t)(A.perm[j] - A.jbase)) << 32;
+  key |= ((uint64_t)((mk[0] + 512) & 0x3ff)) << 20;
+  key |= ((uint64_t)((mk[1] + 512) & 0x3ff)) << 10;
+  key |= ((uint64_t)((mk[2] + 512) & 0x3ff));
+  hsh += splitmix_out(key);
+  cnt += 1;
+}
+
+// Per-lane list of in-range separations waiting for evaluation (LDS,
+// entry e of lane t at base[(e * SW_THREADS + t) * 3]); evaluated by whole
+// waves so that no lane runs the pair code alone.
+constexpr int PL_K = 16;
+constexpr int SW_THREADS_P = 256;
+struct PairList {
+  float* base;
+  int cnt;
+};
+
+template <int PREC, bool DEBUG>
+__device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PairList& L) {
+  for (int e = 0; e < L.cnt; ++e) {
+    const float* q = L.base + e * (SW_THREADS_P * 3);
+    const float dx = q[0], dy = q[1], dz = q[2];
+    pair32(acc, A.p32, dx, dy, dz, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  }
+  L.cnt = 0;
+}
+
+// Visit one neighbour cell `cj` seen through lattice image `m` (in the
+// basis Lred); `dc` is the FP64 vector from the home cell's centre to the
+// centre of that image of cj, `sh` the lattice shift B m in the frame.
+template <int PREC, bool DEBUG>
+__device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
+                                  uint32_t cj, bool zero_image, const double* dc, const int* m,
+                                  const double* oi, const double4& pi64, const int4& wi, PairList& L) {
+  const uint32_t st = A.cstart[A.cell0 + cj] + A.pad, en = A.cstart[A.cell0 + cj + 1] + A.pad;
+  const uint32_t self = zero_image ? s : 0xffffffffu;
+  acc.cand += (en - st) - ((zero_image && s >= st && s < en) ? 1u : 0u);
+  if (PREC == 0) {
+    const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
+    const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
+    const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
+    const double xo = pi64.x - sx, yo = pi64.y - sy, zo = pi64.z - sz;
+    for (uint32_t j0 = st; j0 < en; j0 += 2) {
+      const double4 pa = A.pos64[j0];
+      const double4 pb = A.pos64[min(j0 + 1, en - 1)];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double4 pj = u ? pb : pa;
+        const uint32_t j = j0 + u;
+        const double dx = pj.x - xo, dy = pj.y - yo, dz = pj.z - zo;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 < A.rc2 && j < en && j != self) {
+          pair64(acc, A.p64, dx, dy, dz, r2);
+          acc.pairs += 1;
+          debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
+        }
+      }
+    }
+  } else {
+    // FP64 home position relative to the centre of this image of cj; the
+    // candidates' FP32 offsets are widened to FP64, so the separation is
+    // exact up to the rounding of the stored FP32 offsets
+    const double xo = oi[0] - dc[0], yo = oi[1] - dc[1], zo = oi[2] - dc[2];
+    // four candidate loads in flight per step (indices past the cell are
+    // clamped to its last particle and masked out)
+    for (uint32_t j0 = st; j0 < en; j0 += 4) {
+      const uint32_t jl = en - 1;
+      float4 pj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pj[u] = A.pos32[min(j0 + u, jl)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t j = j0 + u;
+        const double dx = (double)pj[u].x - xo, dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 < g.rc2_hi64 && j < en && j != self) {
+          if (DEBUG || r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
+            // within the rounding band of d_cut, or a close pair: re-evaluate
+            // from the FP64 positions exactly as the FP64 mode does
+            const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
+            const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
+            const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
+            const double xo64 = pi64.x - sx, yo64 = pi64.y - sy, zo64 = pi64.z - sz;
+            const double4 pj64 = A.pos64[j];
+            const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
+            const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+            acc.fp64 += 1;
+            if (e2 < A.rc2) {
+              if (e2 < A.rclose2_64)
+                pair64(acc, A.p64, ex, ey, ez, e2);
+              else
+                pair32(acc, A.p32, (float)ex, (float)ey, (float)ez, (float)e2);
+              acc.pairs += 1;
+              debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
+            }
+          } else {
+            float* q = L.base + L.cnt * (SW_THREADS_P * 3);
+            q[0] = (float)dx;
+            q[1] = (float)dy;
+            q[2] = (float)dz;
+            L.cnt += 1;
+            acc.pairs += 1;
+          }
+        }
+      }
+      if (__ballot(L.cnt > PL_K - 5) != 0) flush_list(acc, A, L);
+    }
+  }
+}
+
+__device__ inline double warp_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// per-particle sweep straight from global memory (used for bricks whose
+// neighbourhood does not fit the LDS tile)
+// ---------------------------------------------------------------------------
+template <int VAR, int PREC, bool DEBUG>
+__device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s, Acc<PREC, DEBUG>& acc,
+                               uint32_t& nbh, PairList& L) {
+  const float4 pi = A.pos32[s];
+  const double4 pi64 = A.pos64[s];
+  const int4 wi = DEBUG ? A.wrap[s] : make_int4(0, 0, 0, 0);
+  const uint32_t hc = __float_as_uint(pi.w);
+  const int a = (int)(hc % (uint32_t)g.nc[0]);
+  const int b = (int)((hc / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
+  const int c = (int)(hc / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
+  double oi[3];
+  cell_centre(g, a, b, c, oi);
+  oi[0] = pi64.x - oi[0];
+  oi[1] = pi64.y - oi[1];
+  oi[2] = pi64.z - oi[2];
+  if (VAR == VAR_DS) {
+    // 27 cells congruent to the box; the unwrapped index a + delta gives
+    // the cell (a + delta) mod c and the lattice image floor((a + delta)/c)
+    int q = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx, ++q) {
+          const int u[3] = {a + dx, b + dy, c + dz};
+          int m[3], w[3];
+          for (int k = 0; k < 3; ++k) {
+            m[k] = idiv_floor32(u[k], g.nc[k]);
+            w[k] = u[k] - m[k] * g.nc[k];
+          }
+          const uint32_t cj = (uint32_t)w[0] + (uint32_t)g.nc[0] * ((uint32_t)w[1] + (uint32_t)g.nc[1] * (uint32_t)w[2]);
+          const bool zero = (dx == 0 && dy == 0 && dz == 0);
+          visit_cell<PREC, DEBUG>(acc, A, g, s, cj, zero, g.ds_delta[q], m, oi, pi64, wi, L);
+          ++nbh;
+        }
+  } else {
+    // rectangular cells of the rotated box; layer k (z) is offset by
+    // k r23 in y, row (j, k) by j r12 + k r13 in x
+    const double w0 = g.w[0], w1 = g.w[1], w2 = g.w[2];
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int C = c + dz;
+      const int k = idiv_floor32(C, g.nc[2]);
+      const int cz = C - k * g.nc[2];
+      const double fy = -(double)k * g.B[5] / w1;
+      const int B0 = (int)floor(b - g.grow[1] + fy);
+      const int B1 = (int)ceil(b + 1 + g.grow[1] + fy) - 1;
+      for (int Bq = B0; Bq <= B1; ++Bq) {
+        const int j = idiv_floor32(Bq, g.nc[1]);
+        const int by = Bq - j * g.nc[1];
+        const double xs = (double)j * g.B[1] + (double)k * g.B[2];
+        const double fx = -xs / w0;
+        const int A0 = (int)floor(a - g.grow[0] + fx);
+        const int A1 = (int)ceil(a + 1 + g.grow[0] + fx) - 1;
+        for (int Aq = A0; Aq <= A1; ++Aq) {
+          const int i = idiv_floor32(Aq, g.nc[0]);
+          const int ax = Aq - i * g.nc[0];
+          const uint32_t cj = (uint32_t)ax + (uint32_t)g.nc[0] * ((uint32_t)by + (uint32_t)g.nc[1] * (uint32_t)cz);
+          const int m[3] = {i, j, k};
+          const double dcv[3] = {(Aq - a) * w0 + xs, (Bq - b) * w1 + (double)k * g.B[5], (C - c) * w2};
+          const bool zero = (i == 0 && j == 0 && k == 0 && cj == hc);
+          visit_cell<PREC, DEBUG>(acc, A, g, s, cj, zero, dcv, m, oi, pi64, wi, L);
+          ++nbh;
+        }
+      }
+    }
+  }
+  if (PREC != 0) flush_list(acc, A, L);
+}
+
+// per-particle outputs: force rotated back to Cartesian for DO, written in
+// the caller's order; debug digest
+template <int VAR, int PREC, bool DEBUG>
+__device__ inline void write_particle(const SweepArgs& A, const CellGeom& g, uint32_t s, const Acc<PREC, DEBUG>& acc) {
+  double F[3];
+  if (PREC == 0) {
+    F[0] = acc.gx; F[1] = acc.gy; F[2] = acc.gz;
+  } else if (PREC == 2) {
+    F[0] = ((double)acc.fx - (double)acc.kx) + acc.gx;
+    F[1] = ((double)acc.fy - (double)acc.ky) + acc.gy;
+    F[2] = ((double)acc.fz - (double)acc.kz) + acc.gz;
+  } else {
+    F[0] = (double)acc.fx + acc.gx;
+    F[1] = (double)acc.fy + acc.gy;
+    F[2] = (double)acc.fz + acc.gz;
+  }
+  double Fc[3];
+  if (VAR == VAR_DO) {
+    for (int r = 0; r < 3; ++r) Fc[r] = g.Q[3 * r] * F[0] + g.Q[3 * r + 1] * F[1] + g.Q[3 * r + 2] * F[2];
+  } else {
+    Fc[0] = F[0]; Fc[1] = F[1]; Fc[2] = F[2];
+  }
+  const uint32_t io = A.perm[s];
+  if (PREC == 0) {
+    double* Fo = (double*)A.F;
+    Fo[3 * (size_t)io] = Fc[0];
+    Fo[3 * (size_t)io + 1] = Fc[1];
+    Fo[3 * (size_t)io + 2] = Fc[2];
+  } else {
+    float* Fo = (float*)A.F;
+    Fo[3 * (size_t)io] = (float)Fc[0];
+    Fo[3 * (size_t)io + 1] = (float)Fc[1];
+    Fo[3 * (size_t)io + 2] = (float)Fc[2];
+  }
+  if (DEBUG) {
+    A.dbg_count[io] = acc.dcount;
+    A.dbg_hash[io] = acc.dhash;
+  }
+}
+
+// energy and virial of one thread as FP64 (u, wxx, wyy, wzz, wxy, wxz, wyz)
+template <int PREC, bool DEBUG>
+__device__ inline void acc_energy(const Acc<PREC, DEBUG>& acc, double* v) {
+  if (PREC == 0) {
+    v[0] = acc.gu;
+    for (int k = 0; k < 6; ++k) v[1 + k] = acc.gw[k];
+  } else {
+    v[0] = (PREC == 2 ? ((double)acc.u - (double)acc.ku) : (double)acc.u) + acc.gu;
+    for (int k = 0; k < 6; ++k) v[1 + k] = (double)acc.w[k];
+  }
+}
+
+// block-wide FP64 sums of v[7] in a fixed order -> partial[8*slot]; integer
+// statistics added atomically.  Every thread of the block must call it.
+__device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const double* v, const uint32_t* st4) {
+  __shared__ double red[4][8];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double t = warp_sum(v[k]);
+    if (lane == 0) red[wid][k] = t;
+  }
+  unsigned long long st[4] = {st4[0], st4[1], st4[2], st4[3]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) st[k] += __shfl_down(st[k], o, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (st[k]) atomicAdd(&A.stats[k], st[k]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const double t = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    A.partial[8 * (size_t)slot + threadIdx.x] = t;
+  }
+}
+
+
+}  // namespace ncl

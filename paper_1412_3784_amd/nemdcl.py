@@ -29,7 +29,11 @@ PRECISIONS = {"fp64": NCL_PREC_FP64, "fp32": NCL_PREC_FP32, "fp32k": NCL_PREC_FP
 
 EXPORTED = ["ncl_create", "ncl_destroy", "ncl_set_potential", "ncl_set_option", "ncl_set_lattice",
             "ncl_get_lattice", "ncl_cell_counts", "ncl_build_cells", "ncl_compute_forces",
-            "ncl_debug_pairs", "ncl_get_stats", "ncl_last_error"]
+            "ncl_debug_pairs", "ncl_get_stats", "ncl_last_error",
+            "ncl_batch_create", "ncl_batch_destroy", "ncl_batch_set_potential", "ncl_batch_set_option",
+            "ncl_batch_set_lattices", "ncl_batch_build_cells", "ncl_batch_compute_forces",
+            "ncl_batch_debug_pairs", "ncl_batch_get_stats", "ncl_batch_get_lattices", "ncl_batch_sllod_run",
+            "ncl_batch_last_error"]
 
 
 class NclError(RuntimeError):
@@ -64,12 +68,25 @@ def _load():
         "ncl_debug_pairs": [P, P, P],
         "ncl_get_stats": [P, ctypes.POINTER(ncl_stats)],
         "ncl_last_error": [P],
+        "ncl_batch_create": [ctypes.POINTER(P), I, P, ctypes.c_int32, P],
+        "ncl_batch_destroy": [P],
+        "ncl_batch_set_potential": [P, D, D, D, I],
+        "ncl_batch_set_option": [P, I, D],
+        "ncl_batch_set_lattices": [P, I, P, P, P, P, P],
+        "ncl_batch_build_cells": [P, P, I, I],
+        "ncl_batch_compute_forces": [P, P, P, P],
+        "ncl_batch_debug_pairs": [P, P, P],
+        "ncl_batch_get_stats": [P, ctypes.POINTER(ncl_stats)],
+        "ncl_batch_get_lattices": [P, P, P],
+        "ncl_batch_sllod_run": [P, P, P, P, P, P, D, D, I64, I, P],
+        "ncl_batch_last_error": [P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
         f.argtypes = args
         f.restype = I
     lib.ncl_last_error.restype = ctypes.c_char_p
+    lib.ncl_batch_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -239,3 +256,162 @@ class Handle:
 
     def stats(self):
         return ncl_get_stats(self.h)
+
+
+# ---- batched form ---------------------------------------------------------
+def _bcheck(b, code: int) -> None:
+    if code != NCL_OK:
+        msg = _lib.ncl_batch_last_error(b).decode() if b else ""
+        raise NclError(code, msg)
+
+
+def ncl_batch_create(n_per_rep, device: int = 0, stream: int = 0):
+    n = _np(n_per_rep, np.int64)
+    b = ctypes.c_void_p()
+    _bcheck(None, _lib.ncl_batch_create(ctypes.byref(b), int(device), ctypes.c_void_p(stream or None),
+                                        len(n), _ptr(n)))
+    return b
+
+
+def ncl_batch_destroy(b) -> None:
+    _bcheck(b, _lib.ncl_batch_destroy(b))
+
+
+def ncl_batch_set_potential(b, eps, sigma, rc, shift_energy) -> None:
+    _bcheck(b, _lib.ncl_batch_set_potential(b, float(eps), float(sigma), float(rc), int(shift_energy)))
+
+
+def ncl_batch_set_option(b, option: int, value: float) -> None:
+    _bcheck(b, _lib.ncl_batch_set_option(b, int(option), float(value)))
+
+
+def ncl_batch_set_lattices(b, variant: int, L0s, As, ts, automorphisms) -> None:
+    R = len(ts)
+    L0 = _np(L0s, np.float64).reshape(R * 9)
+    A = _np(As, np.float64).reshape(R * 9)
+    t = _np(ts, np.float64).reshape(R)
+    naut = np.zeros(R, dtype=np.int32)
+    aut = np.zeros(R * 18, dtype=np.int32)
+    for r, auts in enumerate(automorphisms):
+        naut[r] = len(auts)
+        for k, M in enumerate(auts):
+            aut[18 * r + 9 * k: 18 * r + 9 * k + 9] = _np(M, np.int32).reshape(9)
+    _bcheck(b, _lib.ncl_batch_set_lattices(b, int(variant), _ptr(L0), _ptr(A), _ptr(t), _ptr(naut), _ptr(aut)))
+
+
+def ncl_batch_build_cells(b, x, precision: int, debug: int = 0) -> None:
+    import torch
+    _bcheck(b, _lib.ncl_batch_build_cells(b, _dev_ptr(x, torch.float64), int(precision), int(debug)))
+
+
+def ncl_batch_compute_forces(b, F, U, W) -> None:
+    import torch
+    _bcheck(b, _lib.ncl_batch_compute_forces(b, _dev_ptr(F), _dev_ptr(U, torch.float64), _dev_ptr(W, torch.float64)))
+
+
+def ncl_batch_debug_pairs(b, count, hash_) -> None:
+    import torch
+    _bcheck(b, _lib.ncl_batch_debug_pairs(b, _dev_ptr(count, torch.int64), _dev_ptr(hash_, torch.int64)))
+
+
+def ncl_batch_get_stats(b) -> dict:
+    s = ncl_stats()
+    _bcheck(b, _lib.ncl_batch_get_stats(b, ctypes.byref(s)))
+    return {"n": s.n, "variant": s.variant, "precision": s.precision, "max_occupancy": s.max_occupancy,
+            "ncells": s.ncells, "candidates": s.candidates, "pairs": s.pairs, "fp64_pairs": s.fp64_pairs,
+            "neighbourhood": s.neighbourhood}
+
+
+def ncl_batch_get_lattices(b, nrep: int):
+    L = np.zeros(9 * nrep)
+    c = np.zeros(3 * nrep, dtype=np.int32)
+    _bcheck(b, _lib.ncl_batch_get_lattices(b, _ptr(L), _ptr(c)))
+    return L.reshape(nrep, 3, 3), c.reshape(nrep, 3)
+
+
+def ncl_batch_sllod_run(b, x, p, F, U, W, h, mass, nsteps, use_graph, hist=None) -> None:
+    import torch
+    _bcheck(b, _lib.ncl_batch_sllod_run(b, _dev_ptr(x, torch.float64), _dev_ptr(p, torch.float64), _dev_ptr(F),
+                                        _dev_ptr(U, torch.float64), _dev_ptr(W, torch.float64), float(h),
+                                        float(mass), int(nsteps), int(use_graph),
+                                        _dev_ptr(hist, torch.float64) if hist is not None else None))
+
+
+def ncl_batch_last_error(b) -> str:
+    return _lib.ncl_batch_last_error(b).decode()
+
+
+class Batch:
+    """A batch of independent replicas bound to a device and a torch stream."""
+
+    def __init__(self, n_per_rep, device: int = 0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.n = [int(v) for v in n_per_rep]
+        self.nrep = len(self.n)
+        self.ntot = int(sum(self.n))
+        self.b = ncl_batch_create(self.n, device, self.stream.cuda_stream)
+        self.precision = NCL_PREC_FP32
+
+    def close(self):
+        if self.b is not None:
+            ncl_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_potential(self, pot):
+        ncl_batch_set_potential(self.b, pot.eps, pot.sigma, pot.rc, pot.shift)
+
+    def set_option(self, option, value):
+        ncl_batch_set_option(self.b, option, value)
+
+    def set_lattices(self, variant, L0s, As, ts, automorphisms):
+        ncl_batch_set_lattices(self.b, VARIANTS.get(variant, variant), L0s, As, ts, automorphisms)
+
+    def build_cells(self, x, precision="fp32", debug=False):
+        self.precision = PRECISIONS.get(precision, precision)
+        ncl_batch_build_cells(self.b, x, self.precision, int(debug))
+
+    def _outputs(self, F, U, W):
+        import torch
+        dt = torch.float64 if self.precision == NCL_PREC_FP64 else torch.float32
+        if F is None:
+            F = torch.empty((self.ntot, 3), dtype=dt, device=self.device)
+        if U is None:
+            U = torch.empty(self.nrep, dtype=torch.float64, device=self.device)
+        if W is None:
+            W = torch.empty(self.nrep * 9, dtype=torch.float64, device=self.device)
+        return F, U, W
+
+    def compute_forces(self, F=None, U=None, W=None):
+        F, U, W = self._outputs(F, U, W)
+        ncl_batch_compute_forces(self.b, F, U, W)
+        return F, U, W
+
+    def debug_pairs(self):
+        import torch
+        c = torch.empty(self.ntot, dtype=torch.int64, device=self.device)
+        hs = torch.empty(self.ntot, dtype=torch.int64, device=self.device)
+        ncl_batch_debug_pairs(self.b, c, hs)
+        return c, hs
+
+    def stats(self):
+        return ncl_batch_get_stats(self.b)
+
+    def lattices(self):
+        return ncl_batch_get_lattices(self.b, self.nrep)
+
+    def sllod_run(self, x, p, h, mass, nsteps, use_graph=True, F=None, U=None, W=None, history=False):
+        import torch
+        F, U, W = self._outputs(F, U, W)
+        hist = torch.zeros(((nsteps + 1) * self.nrep * 8,), dtype=torch.float64, device=self.device) if history else None
+        ncl_batch_sllod_run(self.b, x, p, F, U, W, h, mass, nsteps, use_graph, hist)
+        if hist is not None:
+            hist = hist.view(nsteps + 1, self.nrep, 8)
+        return F, U, W, hist

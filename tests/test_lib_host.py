@@ -26,7 +26,7 @@ def header_symbols():
 
 def test_library_exports_every_declared_symbol(ncl):
     syms = header_symbols()
-    assert len(syms) >= 12
+    assert len(syms) >= 24
     lib = ctypes.CDLL(ncl.LIB_PATH)
     for s in syms:
         assert hasattr(lib, s), s

@@ -235,16 +235,19 @@ def config4(replicas: int = 512, n_lo: int = 2048, n_hi: int = 65536) -> List[Bo
 
 
 def config5(replicas: int = 64, n_lo: int = 262144, n_hi: int = 2097152) -> List[Box]:
-    """64 LJ replicas (rho = 0.8), N log-uniform in [n_lo, n_hi], mixed flows,
-    rate uniform in [0.05, 0.5], starting at t = 0."""
+    """64 LJ replicas (rho = 0.8), N log-uniform in [n_lo, n_hi] rounded to the
+    nearest cube g^3, mixed flows, rate uniform in [0.05, 0.5], starting at
+    t = 0 from a g^3 grid of sites with 0.05 Gaussian jitter (uniform random
+    sites overlap and would blow up under dynamics)."""
     out = []
     for r in range(replicas):
         g = _rng(5000 + r)
         n = int(round(math.exp(g.uniform(math.log(n_lo), math.log(n_hi)))))
+        side = max(2, int(round(n ** (1.0 / 3.0))))
         flow = FLOWS[int(g.integers(0, 3))]
         rate = float(g.uniform(0.05, 0.5))
-        out.append(make_box(flow, rate, n, density=0.8, pot=LJ25, t=0.0,
-                            seed=50000 + r, name=f"nemd{r}_{flow}"))
+        out.append(make_box(flow, rate, side ** 3, density=0.8, pot=LJ25, t=0.0,
+                            seed=50000 + r, name=f"nemd{r}_{flow}", grid=side, jitter_sigma=0.05))
     return out
 
 
