@@ -173,11 +173,18 @@ __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, Pai
 // Visit one neighbour cell `cj` seen through lattice image `m` (in the
 // basis Lred); `dc` is the FP64 vector from the home cell's centre to the
 // centre of that image of cj, `sh` the lattice shift B m in the frame.
-template <int PREC, bool DEBUG>
+//
+// FLAT: the slots [cstart[cj], cstart[cj + ncell]) of ncell consecutive x
+// cells of one row (cells are stored x-fastest), for the rectangular cells
+// of the dynamic-offset list, whose x step (w0, 0, 0) only changes d_x; dc
+// is then the centre offset of the row's x cell 0 and each candidate adds
+// ax_j w0, ax_j being its cell's x index (cell id - row base).
+template <int PREC, bool DEBUG, bool FLAT = false>
 __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
                                   uint32_t cj, bool zero_image, const double* dc, const int* m,
-                                  const double* oi, const double4& pi64, const int4& wi, PairList& L) {
-  const uint32_t st = A.cstart[A.cell0 + cj] + A.pad, en = A.cstart[A.cell0 + cj + 1] + A.pad;
+                                  const double* oi, const double4& pi64, const int4& wi, PairList& L,
+                                  uint32_t ncell = 1, uint32_t rowbase = 0) {
+  const uint32_t st = A.cstart[A.cell0 + cj] + A.pad, en = A.cstart[A.cell0 + cj + ncell] + A.pad;
   const uint32_t self = zero_image ? s : 0xffffffffu;
   acc.cand += (en - st) - ((zero_image && s >= st && s < en) ? 1u : 0u);
   if (PREC == 0) {
@@ -216,7 +223,9 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const uint32_t j = j0 + u;
-        const double dx = (double)pj[u].x - xo, dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
+        double dx = (double)pj[u].x - xo;
+        if (FLAT) dx = fma((double)(int32_t)(__float_as_uint(pj[u].w) - rowbase), g.w[0], dx);
+        const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
         const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
         if (r2 < g.rc2_hi64 && j < en && j != self) {
           if (DEBUG || r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
@@ -314,15 +323,17 @@ __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s
         const double fx = -xs / w0;
         const int A0 = (int)floor(a - g.grow[0] + fx);
         const int A1 = (int)ceil(a + 1 + g.grow[0] + fx) - 1;
-        for (int Aq = A0; Aq <= A1; ++Aq) {
-          const int i = idiv_floor32(Aq, g.nc[0]);
-          const int ax = Aq - i * g.nc[0];
-          const uint32_t cj = (uint32_t)ax + (uint32_t)g.nc[0] * ((uint32_t)by + (uint32_t)g.nc[1] * (uint32_t)cz);
+        const uint32_t rowbase = (uint32_t)g.nc[0] * ((uint32_t)by + (uint32_t)g.nc[1] * (uint32_t)cz);
+        // the row's cells A0..A1, one contiguous run per x image i
+        for (int i = idiv_floor32(A0, g.nc[0]); i <= idiv_floor32(A1, g.nc[0]); ++i) {
+          const int axlo = max(A0 - i * g.nc[0], 0), axhi = min(A1 - i * g.nc[0], g.nc[0] - 1);
           const int m[3] = {i, j, k};
-          const double dcv[3] = {(Aq - a) * w0 + xs, (Bq - b) * w1 + (double)k * g.B[5], (C - c) * w2};
-          const bool zero = (i == 0 && j == 0 && k == 0 && cj == hc);
-          visit_cell<PREC, DEBUG>(acc, A, g, s, cj, zero, dcv, m, oi, pi64, wi, L);
-          ++nbh;
+          // centre offset of x cell 0 of this image of the row
+          const double dcv[3] = {(double)(i * g.nc[0] - a) * w0 + xs, (Bq - b) * w1 + (double)k * g.B[5], (C - c) * w2};
+          const bool zero = (i == 0 && j == 0 && k == 0);
+          visit_cell<PREC, DEBUG, PREC != 0>(acc, A, g, s, rowbase + (uint32_t)axlo, zero, dcv, m, oi, pi64, wi, L,
+                                             (uint32_t)(axhi - axlo + 1), rowbase);
+          nbh += (uint32_t)(axhi - axlo + 1);
         }
       }
     }
