@@ -72,7 +72,7 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 20)
     p.add_argument("--variant", default="do", choices=["do", "ds"])
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp32k", "fp64"])
-    p.add_argument("--sweep", default="particle", choices=["tiled", "particle"])
+    p.add_argument("--sweep", default="auto", choices=["tiled", "particle", "auto"])
     p.add_argument("--replicas", type=int, default=None, help="batch/nemd: number of replicas")
     p.add_argument("--no-batch", action="store_true", help="plain: skip the batched comparison")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -123,7 +123,8 @@ def run_plain(a, out):
     b0 = boxes[0]
     h = Handle(0, stream)
     h.set_potential(b0.pot)
-    h.set_option(ncl.NCL_OPT_SWEEP, 0 if a.sweep == "tiled" else 1)
+    h.set_option(ncl.NCL_OPT_SWEEP, {"tiled": ncl.NCL_SWEEP_TILED, "particle": ncl.NCL_SWEEP_PARTICLE,
+                                     "auto": ncl.NCL_SWEEP_AUTO}[a.sweep])
     # positions for every strain value: the fixed fractional configuration
     # carried by the flow, x_k = L(t_k) s, resident in HBM before timing
     s = torch.from_numpy(b0.frac).to(dev)
@@ -149,12 +150,16 @@ def run_plain(a, out):
         if ev is not None:
             ev[2].record(stream)
 
-    # pair and candidate counts per strain value (untimed)
+    # pair and candidate counts per strain value (untimed; the autotuner
+    # settles the schedule of every strain's workload class here)
     pairs, cands = np.zeros(64), np.zeros(64)
+    sched = {}
     for k in range(64):
         step(k)
         st = h.stats()
         pairs[k], cands[k] = st["pairs"] / 2, st["candidates"]
+        key = ("tiled" + "x".join(map(str, st["brick"]))) if st["sweep"] == 0 else "particle"
+        sched[key] = sched.get(key, 0) + 1
     for k in range(a.warmup):
         step(k)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
@@ -182,10 +187,11 @@ def run_plain(a, out):
                    "variant": a.variant, "precision": a.precision, "sweep": a.sweep, "rate": 0.5,
                    "density": 0.8, "rc": 2.5},
         "breakdown_ms": {"build": 1e3 * t_build / a.steps, "force": 1e3 * t_force / a.steps},
+        "schedule": sched,
         "candidates_per_particle": tot_cands / (a.steps * n),
         "search_efficiency": 2 * tot_pairs / tot_cands,
         "roofline": roofline_alu(tot_cands, tot_pairs, t_force, a.steps,
-                                 f"k_sweep_{a.sweep}<{a.variant},{a.precision}>", n),
+                                 f"sweep[{a.sweep}]<{a.variant},{a.precision}>", n),
     })
     h.close()
     return boxes

@@ -73,7 +73,13 @@ extern "C" {
 #define NCL_OPT_BAND 2           /* FP32 modes: relative half-width of the r^2 band
                                     re-decided in FP64 (default 1e-5)             */
 #define NCL_OPT_SWEEP 3          /* sweep kernel: 0 = LDS-tiled bricks of cells,
-                                    1 = one thread per particle (default 1)       */
+                                    1 = one thread per particle, 2 = autotuned
+                                    (default): the first force pass of each
+                                    workload class (variant, precision, cells per
+                                    axis, occupancy) times the per-particle sweep
+                                    and the tiled sweep with its three best-ranked
+                                    bricks on the handle's stream, synchronising
+                                    once, and keeps the fastest                   */
 
 typedef struct ncl_ctx *ncl_handle;
 
@@ -81,13 +87,18 @@ typedef struct {
     int64_t n;              /* particles binned                                   */
     int32_t variant;        /* NCL_DYNAMIC_SIZE / NCL_DYNAMIC_OFFSET              */
     int32_t precision;      /* NCL_PREC_*                                         */
-    int32_t cells[3];       /* c_i (Sec. 4.1) or l_i (Sec. 5.2)                   */
+    int32_t cells[3];       /* c_i (Sec. 4.1) or l_i (Sec. 4.2)                   */
     int32_t max_occupancy;  /* most particles in one cell                         */
     int64_t ncells;
     int64_t candidates;     /* distance checks, each ordered (i, j-image) once    */
     int64_t pairs;          /* in-range ordered pairs: twice the interacting set  */
     int64_t fp64_pairs;     /* FP32 modes: pairs re-evaluated in FP64             */
     int64_t neighbourhood;  /* sum over particles of neighbourhood cells visited   */
+    int32_t sweep;          /* schedule of the last force pass: 0 tiled, 1 per particle */
+    int32_t brick[3];       /* its brick of cells when tiled                      */
+    float tune_ms[4];       /* autotuner timings of this workload class: per
+                               particle, then tiled with the three best-ranked
+                               bricks (-1: not timed)                             */
 } ncl_stats;
 
 /* Create a handle on HIP device `device` that enqueues on `stream` (a

@@ -26,7 +26,7 @@ struct ncl_ctx {
   double eps = 1.0, sigma = 1.0, rc = 1.122462048309373, shift_on = 1.0;
   // options
   int do_tight = 1;
-  int sweep_mode = SWEEP_PARTICLE;
+  int sweep_mode = SWEEP_AUTO;
   double close_r = 0.45, band = 1e-5;
   // lattice
   bool have_lattice = false;
@@ -53,6 +53,20 @@ struct ncl_ctx {
   uint32_t* overflow = nullptr;
   size_t cap_bricks = 0;
   int brick[6] = {1, 1, 1, 1, 1, 1};  // sx, sy, sz, nbx, nby, nbz
+  // autotuner: candidate brick shapes of the current build (best first) and
+  // the schedule chosen per workload class
+  int ncand = 0;
+  int cand[3][6];
+  struct Tuned {
+    uint64_t key;
+    int mode;
+    int brick[6];
+    float ms[4];
+  };
+  std::vector<Tuned> tuned;
+  Tuned last{};
+  int used_mode = SWEEP_PARTICLE;  // schedule of the last force pass
+  int used_brick[3] = {0, 0, 0};
   double* dbgF = nullptr;  // internal F/U/W for ncl_debug_pairs
   // small device words: [0..3] stats (u64), then maxocc (u32), err (i32)
   unsigned long long* small = nullptr;
@@ -145,7 +159,8 @@ int ncl_set_option(ncl_handle h, int option, double value) {
       h->close_r = value;
       break;
     case NCL_OPT_SWEEP:
-      if (value != 0.0 && value != 1.0) return fail(h, NCL_E_ARG, "sweep mode must be 0 (tiled) or 1 (per particle)");
+      if (value != 0.0 && value != 1.0 && value != 2.0)
+        return fail(h, NCL_E_ARG, "sweep mode must be 0 (tiled), 1 (per particle) or 2 (autotuned)");
       h->sweep_mode = (int)value;
       break;
     case NCL_OPT_BAND:
@@ -259,13 +274,17 @@ int ncl_cell_counts(ncl_handle h, int variant, int32_t counts[3]) {
 // particles as the 256 lanes can hold while the staged neighbourhood (home
 // cells plus a rim of one or two cells, per variant) stays well inside the
 // LDS tile.  Sizes come from the mean cell occupancy.
+// Brick shapes for the LDS-tiled sweep, ranked by a model of useful home
+// particles against staged neighbourhood size; the best three are kept as
+// candidates for the autotuner and the best one is the default.
 static void choose_brick(ncl_ctx* h, const CellGeom& g, size_t n, uint32_t nc) {
   const double occ = nc ? (double)n / nc : 1.0;
   // staged rim: DS adds one cell each side; DO adds the cells overlapping a
   // band of d_cut (about 2.5-3 cells per axis with offset rows)
   const double rim = (g.variant == VAR_DO) ? 2.6 : 2.0;
-  double best = -1e300;
-  int bs[3] = {1, 1, 1};
+  double best[3] = {-1e300, -1e300, -1e300};
+  int bs[3][3] = {{1, 1, 1}, {1, 1, 1}, {1, 1, 1}};
+  int found = 0;
   for (int sz = 1; sz <= g.nc[2] && sz <= 6; ++sz)
     for (int sy = 1; sy <= g.nc[1] && sy <= 12; ++sy)
       for (int sx = 1; sx <= g.nc[0] && sx <= 24; ++sx) {
@@ -275,15 +294,25 @@ static void choose_brick(ncl_ctx* h, const CellGeom& g, size_t n, uint32_t nc) {
         const double tile = occ * cells;
         if (rows > 56 || cells > 800 || sy * sz > 48 || tile > 0.86 * 2240) continue;
         const double score = fmin(home, 244.0) - 0.03 * tile;
-        if (score > best) {
-          best = score;
-          bs[0] = sx; bs[1] = sy; bs[2] = sz;
-        }
+        ++found;
+        for (int r = 0; r < 3; ++r)
+          if (score > best[r]) {
+            for (int q = 2; q > r; --q) {
+              best[q] = best[q - 1];
+              for (int k = 0; k < 3; ++k) bs[q][k] = bs[q - 1][k];
+            }
+            best[r] = score;
+            bs[r][0] = sx; bs[r][1] = sy; bs[r][2] = sz;
+            break;
+          }
       }
-  for (int k = 0; k < 3; ++k) {
-    h->brick[k] = bs[k];
-    h->brick[3 + k] = (g.nc[k] + bs[k] - 1) / bs[k];
-  }
+  h->ncand = found < 1 ? 1 : (found < 3 ? found : 3);
+  for (int r = 0; r < h->ncand; ++r)
+    for (int k = 0; k < 3; ++k) {
+      h->cand[r][k] = bs[r][k];
+      h->cand[r][3 + k] = (g.nc[k] + bs[r][k] - 1) / bs[r][k];
+    }
+  for (int k = 0; k < 6; ++k) h->brick[k] = h->cand[0][k];
 }
 
 int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int precision, int debug) {
@@ -342,7 +371,9 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   }
   choose_brick(h, g, (size_t)n, nc);
   {
-    const size_t nbr = std::max((size_t)h->brick[3] * h->brick[4] * h->brick[5], ((size_t)n + 255) / 256);
+    size_t nbr = ((size_t)n + 255) / 256;
+    for (int r = 0; r < h->ncand; ++r)
+      nbr = std::max(nbr, (size_t)h->cand[r][3] * h->cand[r][4] * h->cand[r][5]);
     if (nbr + 2 > h->cap_bricks || !h->overflow) {
       if (h->overflow) HIPCHK(h, hipFree(h->overflow));
       if (h->partial) HIPCHK(h, hipFree(h->partial));
@@ -387,6 +418,38 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   return NCL_OK;
 }
 
+// brick-dependent fields of the LDS-tiled sweep: the brick shape and the
+// FP32 screening band and residual unit that follow from its extent
+static void brick_args(const ncl_ctx* h, SweepArgs* A) {
+  const double rc2 = h->rc * h->rc;
+  A->sx = h->brick[0];
+  A->sy = h->brick[1];
+  A->sz = h->brick[2];
+  A->nbx = h->brick[3];
+  A->nby = h->brick[4];
+  A->nbz = h->brick[5];
+  // largest brick-frame coordinate: half the brick plus the rim of staged
+  // cells, per axis, through the cell step vectors
+  const CellGeom& g = h->geom;
+  const double ext[3] = {0.5 * A->sx + 4.0, 0.5 * A->sy + 4.0, 0.5 * A->sz + 3.0};
+  double xmax = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) s += fabs(g.cen[3 * r + c]) * ext[c];
+    xmax = fmax(xmax, s);
+  }
+  const double rc = h->rc;
+  // FP32 screening: each coordinate is off by at most half an ulp of xmax,
+  // the difference by one more half ulp; bound the r^2 error and double it
+  const double dd = ulp32(xmax) + 0.5 * ulp32(2.0 * rc);
+  const double dr2 = 2.0 * rc * sqrt(3.0) * dd + 3.0 * dd * dd + 2.0 * ulp32(rc2);
+  A->rc2c = nextafterf((float)(rc2 + 2.0 * dr2), INFINITY);
+  // residual unit: half an ulp of xmax spans 16384 units of the int16
+  A->res_unit = ulp32(xmax) / 32768.0;
+  const double dfine = A->res_unit + 4e-16 * xmax;
+  A->band64 = 4.0 * (2.0 * rc * sqrt(3.0) * dfine + 1e-15 * rc2);
+}
+
 static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
   const double s2 = h->sigma * h->sigma;
   double shift = 0.0;
@@ -421,38 +484,81 @@ static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
   A->p64.eps48 = 48.0 * h->eps;
   A->p64.shift = shift;
   A->overflow = h->overflow;
-  A->sx = h->brick[0];
-  A->sy = h->brick[1];
-  A->sz = h->brick[2];
-  A->nbx = h->brick[3];
-  A->nby = h->brick[4];
-  A->nbz = h->brick[5];
-  // largest brick-frame coordinate: half the brick plus the rim of staged
-  // cells, per axis, through the cell step vectors
-  const CellGeom& g = h->geom;
-  const double ext[3] = {0.5 * A->sx + 4.0, 0.5 * A->sy + 4.0, 0.5 * A->sz + 3.0};
-  double xmax = 0.0;
-  for (int r = 0; r < 3; ++r) {
-    double s = 0.0;
-    for (int c = 0; c < 3; ++c) s += fabs(g.cen[3 * r + c]) * ext[c];
-    xmax = fmax(xmax, s);
-  }
-  const double rc = h->rc;
-  // FP32 screening: each coordinate is off by at most half an ulp of xmax,
-  // the difference by one more half ulp; bound the r^2 error and double it
-  const double dd = ulp32(xmax) + 0.5 * ulp32(2.0 * rc);
-  const double dr2 = 2.0 * rc * sqrt(3.0) * dd + 3.0 * dd * dd + 2.0 * ulp32(rc2);
-  A->rc2c = nextafterf((float)(rc2 + 2.0 * dr2), INFINITY);
-  // residual unit: half an ulp of xmax spans 16384 units of the int16
-  A->res_unit = ulp32(xmax) / 32768.0;
-  const double dfine = A->res_unit + 4e-16 * xmax;
-  A->band64 = 4.0 * (2.0 * rc * sqrt(3.0) * dfine + 1e-15 * rc2);
+  brick_args(h, A);
   A->rclose2_64 = h->close_r * h->close_r * s2;
   A->p32.sig2 = (float)s2;
   A->p32.eps4 = (float)(4.0 * h->eps);
   A->p32.eps24 = (float)(24.0 * h->eps);
   A->p32.eps48 = (float)(48.0 * h->eps);
   A->p32.shift = (float)shift;
+}
+
+// Workload class for the autotuner: variant, precision, cells per axis and
+// occupancy in quarter-octaves; a schedule is re-tuned when any changes.
+static uint64_t tune_key(const ncl_ctx* h) {
+  const double occ = h->ncells ? (double)h->n / h->ncells : 0.0;
+  const int ob = occ > 0.0 ? (int)floor(4.0 * log2(occ)) + 64 : 0;
+  uint64_t k = (uint64_t)h->geom.variant | ((uint64_t)h->precision << 2) | ((uint64_t)(ob & 0xff) << 4);
+  for (int a = 0; a < 3; ++a) k |= (uint64_t)(h->geom.nc[a] & 0xffff) << (12 + 16 * a);
+  return k;
+}
+
+static hipError_t sweep_with(ncl_ctx* h, SweepArgs* A, int mode, const int* brick, void* F, double* U, double* W) {
+  for (int k = 0; k < 6; ++k) h->brick[k] = brick[k];
+  brick_args(h, A);
+  SweepLaunch L;
+  L.mode = mode;
+  L.g = &h->geom;
+  L.args = A;
+  L.precision = h->precision;
+  L.debug = false;
+  L.U = U;
+  L.W = W;
+  return launch_sweep(L, h->stream);
+}
+
+// Autotuner: time each candidate schedule once on the caller's stream (after
+// one untimed launch) with HIP events; the fastest is cached for the class.
+static int autotune(ncl_ctx* h, SweepArgs* A, void* F, double* U, double* W, ncl_ctx::Tuned* out) {
+  int modes[4], bricks[4][6], nc = 0;
+  modes[nc] = SWEEP_PARTICLE;
+  for (int k = 0; k < 6; ++k) bricks[nc][k] = h->cand[0][k];
+  ++nc;
+  for (int r = 0; r < h->ncand && nc < 4; ++r, ++nc) {
+    modes[nc] = SWEEP_TILED;
+    for (int k = 0; k < 6; ++k) bricks[nc][k] = h->cand[r][k];
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  int best = 0;
+  float bms = 3.0e38f;
+  out->key = tune_key(h);
+  for (int c = 0; c < 4; ++c) out->ms[c] = -1.0f;
+  for (int c = 0; c < nc; ++c) {
+    hipError_t e = sweep_with(h, A, modes[c], bricks[c], F, U, W);
+    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+    if (e == hipSuccess) e = sweep_with(h, A, modes[c], bricks[c], F, U, W);
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return hip_fail(h, e, "autotune");
+    }
+    out->ms[c] = ms;
+    if (ms < bms) {
+      bms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  out->mode = modes[best];
+  for (int k = 0; k < 6; ++k) out->brick[k] = bricks[best][k];
+  return NCL_OK;
 }
 
 int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
@@ -462,16 +568,29 @@ int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
   HIPCHK(h, hipSetDevice(h->device));
   SweepArgs A;
   fill_sweep_args(h, &A, F);
-  SweepLaunch L;
-  L.mode = h->sweep_mode;
-  L.g = &h->geom;
-  L.args = &A;
-  L.precision = h->precision;
-  L.debug = false;
-  L.U = U;
-  L.W = W;
-  hipError_t e = launch_sweep(L, h->stream);
+  int mode = h->sweep_mode;
+  int brick[6];
+  for (int k = 0; k < 6; ++k) brick[k] = h->cand[0][k];
+  if (mode == SWEEP_AUTO) {
+    const uint64_t key = tune_key(h);
+    const ncl_ctx::Tuned* t = nullptr;
+    for (const auto& e : h->tuned)
+      if (e.key == key) t = &e;
+    if (!t) {
+      ncl_ctx::Tuned nt{};
+      const int rc = autotune(h, &A, F, U, W, &nt);
+      if (rc) return rc;
+      h->tuned.push_back(nt);
+      t = &h->tuned.back();
+    }
+    h->last = *t;
+    mode = t->mode;
+    for (int k = 0; k < 6; ++k) brick[k] = t->brick[k];
+  }
+  hipError_t e = sweep_with(h, &A, mode, brick, F, U, W);
   if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
+  h->used_mode = mode;
+  for (int k = 0; k < 3; ++k) h->used_brick[k] = mode == SWEEP_TILED ? brick[k] : 0;
   return NCL_OK;
 }
 
@@ -486,7 +605,12 @@ int ncl_debug_pairs(ncl_handle h, int64_t* count, uint64_t* hash) {
   A.dbg_count = count;
   A.dbg_hash = hash;
   SweepLaunch L;
-  L.mode = h->sweep_mode;
+  L.mode = h->sweep_mode == SWEEP_AUTO ? (h->last.key == tune_key(h) ? h->last.mode : SWEEP_PARTICLE) : h->sweep_mode;
+  if (L.mode == SWEEP_TILED) {
+    const int* b = h->sweep_mode == SWEEP_AUTO ? h->last.brick : h->cand[0];
+    for (int k = 0; k < 6; ++k) h->brick[k] = b[k];
+    brick_args(h, &A);
+  }
   L.g = &h->geom;
   L.args = &A;
   L.precision = h->precision;
@@ -516,6 +640,12 @@ int ncl_get_stats(ncl_handle h, ncl_stats* out) {
   out->fp64_pairs = (int64_t)w[2];
   out->neighbourhood = (int64_t)w[3];
   out->max_occupancy = (int32_t)(uint32_t)(w[4] & 0xffffffffull);
+  out->sweep = h->used_mode;
+  for (int k = 0; k < 3; ++k) out->brick[k] = h->used_brick[k];
+  for (int k = 0; k < 4; ++k) out->tune_ms[k] = -1.0f;
+  for (const auto& t : h->tuned)
+    if (t.key == tune_key(h))
+      for (int k = 0; k < 4; ++k) out->tune_ms[k] = t.ms[k];
   const int errw = (int)(uint32_t)(w[5] & 0xffffffffull);
   if (errw) {
     int zero = 0;

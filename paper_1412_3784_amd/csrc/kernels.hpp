@@ -57,7 +57,7 @@ struct BuildLaunch {
   int* err;
 };
 
-enum { SWEEP_TILED = 0, SWEEP_PARTICLE = 1 };
+enum { SWEEP_TILED = 0, SWEEP_PARTICLE = 1, SWEEP_AUTO = 2 };
 
 struct SweepLaunch {
   int mode;  // SWEEP_TILED or SWEEP_PARTICLE

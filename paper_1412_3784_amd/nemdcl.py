@@ -23,6 +23,7 @@ NCL_E_HIP, NCL_E_DEVICE_FLAG, NCL_E_STATE = -5, -6, -7
 NCL_DYNAMIC_SIZE, NCL_DYNAMIC_OFFSET = 0, 1
 NCL_PREC_FP64, NCL_PREC_FP32, NCL_PREC_FP32_KAHAN = 0, 1, 2
 NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS, NCL_OPT_BAND, NCL_OPT_SWEEP = 0, 1, 2, 3
+NCL_SWEEP_TILED, NCL_SWEEP_PARTICLE, NCL_SWEEP_AUTO = 0, 1, 2
 
 VARIANTS = {"ds": NCL_DYNAMIC_SIZE, "do": NCL_DYNAMIC_OFFSET}
 PRECISIONS = {"fp64": NCL_PREC_FP64, "fp32": NCL_PREC_FP32, "fp32k": NCL_PREC_FP32_KAHAN}
@@ -46,7 +47,8 @@ class ncl_stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("variant", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("cells", ctypes.c_int32 * 3), ("max_occupancy", ctypes.c_int32), ("ncells", ctypes.c_int64),
                 ("candidates", ctypes.c_int64), ("pairs", ctypes.c_int64), ("fp64_pairs", ctypes.c_int64),
-                ("neighbourhood", ctypes.c_int64)]
+                ("neighbourhood", ctypes.c_int64), ("sweep", ctypes.c_int32), ("brick", ctypes.c_int32 * 3),
+                ("tune_ms", ctypes.c_float * 4)]
 
 
 def _load():
@@ -183,7 +185,8 @@ def ncl_get_stats(h) -> dict:
     _check(h, _lib.ncl_get_stats(h, ctypes.byref(s)))
     return {"n": s.n, "variant": s.variant, "precision": s.precision, "cells": list(s.cells),
             "max_occupancy": s.max_occupancy, "ncells": s.ncells, "candidates": s.candidates,
-            "pairs": s.pairs, "fp64_pairs": s.fp64_pairs, "neighbourhood": s.neighbourhood}
+            "pairs": s.pairs, "fp64_pairs": s.fp64_pairs, "neighbourhood": s.neighbourhood,
+            "sweep": s.sweep, "brick": list(s.brick), "tune_ms": list(s.tune_ms)}
 
 
 def ncl_last_error(h) -> str:

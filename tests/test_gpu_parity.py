@@ -177,3 +177,27 @@ def test_clustered_input_uses_fallback(variant):
         for prec in PRECS:
             gres = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
             compare(gres, r, prec, label=f"cluster/{variant}/{prec}/sweep{sweep}")
+
+
+@pytest.mark.parametrize("variant", VARS)
+def test_autotuned_sweep_matches_oracle(variant):
+    """The default schedule: the autotuner times the per-particle sweep and
+    tiled bricks on the first pass, keeps the fastest, and every schedule it
+    can pick meets the same parity bar (pair digests need the debug pass,
+    which reuses the chosen schedule)."""
+    from paper_1412_3784_amd import Handle, nemdcl
+    box = wl.config2(k=21, n=65536)
+    x = oracle_positions(box)
+    r = run_oracle(box, x)
+    h = Handle(0)
+    g1 = run_gpu(box, x, variant, "fp32", handle=h)
+    st = h.stats()
+    assert st["sweep"] in (nemdcl.NCL_SWEEP_TILED, nemdcl.NCL_SWEEP_PARTICLE)
+    timed = [t for t in st["tune_ms"] if t >= 0]
+    assert len(timed) >= 2 and min(timed) > 0
+    compare(g1, r, "fp32", label=f"auto/{variant}")
+    # a second pass of the same class reuses the choice without re-timing
+    g2 = run_gpu(box, x, variant, "fp32", handle=h)
+    assert h.stats()["tune_ms"] == st["tune_ms"] and h.stats()["sweep"] == st["sweep"]
+    assert (g1["F"] == g2["F"]).all()
+    h.close()
