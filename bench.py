@@ -11,6 +11,8 @@ Workloads (--workload):
   batch  the 512-replica batch alone as the headline.
   nemd   SLLOD steps (h = 0.002) of 64 LJ replicas, N log-uniform in
          [262144, 2097152], captured as one HIP graph per step.
+  longrun the long-run neighbourhood experiment of Sec. 5.3 with measured
+         candidate and pair counts (search efficiency of both lists).
 
 value = pair interactions / s: interacting pairs (each unordered pair once)
 summed over the timed steps, divided by the wall time of those steps.
@@ -68,7 +70,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=64)
     p.add_argument("--warmup", type=int, default=4)
-    p.add_argument("--workload", default="plain", choices=["plain", "batch", "nemd"])
+    p.add_argument("--workload", default="plain", choices=["plain", "batch", "nemd", "longrun"])
     p.add_argument("--n", type=int, default=1 << 20)
     p.add_argument("--variant", default="do", choices=["do", "ds"])
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp32k", "fp64"])
@@ -361,6 +363,80 @@ def run_nemd(a, out):
     return boxes
 
 
+def longrun_measure(samples=200, periods=20, density=100.0, seed=0):
+    """The long-run experiment of Sec. 5.3 with measured counts: a box of
+    initial side 10 d_cut (d_cut = (3/4pi)^(1/3), sphere volume one) under
+    uniaxial flow diag(0.05, -0.025, -0.025) with generalised KR remaps;
+    uniform particles carried by the flow; at each sampled time the GPU
+    lists count candidates and in-range pairs.  Returns the measured search
+    efficiencies (in-range pairs / candidates over the run) of the
+    dynamic-size list and of the dynamic-offset list with the paper's
+    neighbourhood (grown by whole cells) and with the tight one (grown by
+    d_cut), and the geometric efficiencies 1 / <neighbourhood volume> at the
+    same times."""
+    import torch
+    from paper_1412_3784_amd import Handle
+    from paper_1412_3784_amd import nemdcl as ncl
+    dcut = (3.0 / (4.0 * np.pi)) ** (1.0 / 3.0)
+    side = 10.0 * dcut
+    n = int(round(density * side ** 3))
+    box = wl.make_box("uniaxial", 0.05, n, side=side, t=0.0, seed=seed)
+    ts = np.linspace(0.0, periods * box.period, samples, endpoint=False)
+    dev = torch.device("cuda:0")
+    s = torch.from_numpy(box.frac).to(dev)
+    out = {}
+    geo = {"ds": [], "do_paper": []}
+    for name, variant, tight in (("ds", "ds", 1.0), ("do_paper", "do", 0.0), ("do_tight", "do", 1.0)):
+        h = Handle(0)
+        h.set_potential(eps=1.0, sigma=dcut / 2 ** (1 / 6), rc=dcut, shift=1)
+        h.set_option(ncl.NCL_OPT_DO_TIGHT, tight)
+        # the per-particle sweep visits exactly each particle's neighbourhood
+        # (the tiled sweep's counts include its bricks' staging)
+        h.set_option(ncl.NCL_OPT_SWEEP, ncl.NCL_SWEEP_PARTICLE)
+        cand = pairs = 0
+        for t in ts:
+            h.set_lattice(box.L0, box.A, t, [])
+            Lt, _, _ = h.get_lattice()
+            x = (s @ torch.from_numpy(Lt).to(dev).T).contiguous()
+            h.set_lattice(box.L0, box.A, t, box.automorphisms)
+            h.build_cells(variant, x, "fp32")
+            h.compute_forces()
+            st = h.stats()
+            cand += st["candidates"]
+            pairs += st["pairs"]
+            if name in geo:
+                Lr, _, _ = h.get_lattice()
+                V = abs(np.linalg.det(Lr))
+                c = np.array(st["cells"], dtype=float)
+                if variant == "ds":
+                    geo[name].append(27.0 * V / c.prod())
+                else:
+                    geo[name].append((27.0 + 14.0 / c[2] + 6.0 / c[1] - 4.0 / (c[1] * c[2])) * V / c.prod())
+        h.close()
+        out[name] = pairs / cand
+    out["geometric_ds"] = 1.0 / np.mean(geo["ds"])
+    out["geometric_do_paper"] = 1.0 / np.mean(geo["do_paper"])
+    out["n"] = n
+    out["samples"] = samples
+    out["periods"] = periods
+    return out
+
+
+def run_longrun(a, out):
+    t0 = time.perf_counter()
+    r = longrun_measure(samples=a.steps if a.steps != 64 else 200)
+    wall = time.perf_counter() - t0
+    out.update({
+        "metric": "long-run search efficiency (in-range pairs / candidates), dynamic offset",
+        "value": r["do_tight"], "unit": "ratio", "steps": r["samples"], "ms_per_step": 1e3 * wall / r["samples"],
+        "dtype": "f32 (f64 lattice)",
+        "config": {"workload": f"uniaxial_0.05_side10dcut_N{r['n']}_{r['periods']}periods", "n": r["n"]},
+        "measured": {k: r[k] for k in ("ds", "do_paper", "do_tight")},
+        "geometric": {"ds": r["geometric_ds"], "do_paper": r["geometric_do_paper"]},
+        "paper": {"ds": 0.0688, "do": 0.123},
+    })
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -379,6 +455,8 @@ def main():
             out["batched"]["workload"] = f"wca_rho0.8442_{r['replicas']}replicas_N{r['n_total']}_{a.variant}"
     elif a.workload == "batch":
         boxes = run_batch(a, out)
+    elif a.workload == "longrun":
+        run_longrun(a, out)
     else:
         boxes = run_nemd(a, out)
     if not a.no_copy_probe:

@@ -364,40 +364,39 @@ NCL_HD uint32_t locate(const CellGeom& g, const double* x, double* xw, int32_t* 
   }
   if (g.variant == VAR_DS) {
     // fractional coordinates s = Lred^-1 x, wrapped into [0,1)
-    double s[3];
+    double s[3], n[3];
     for (int i = 0; i < 3; ++i) s[i] = g.Finv[3 * i] * x[0] + g.Finv[3 * i + 1] * x[1] + g.Finv[3 * i + 2] * x[2];
     for (int i = 0; i < 3; ++i) {
       double fl = floor(s[i]);
       double f = s[i] - fl;
       if (f >= 1.0) { f = 0.0; fl += 1.0; }
-      fl = fmin(fmax(fl, -1073741824.0), 1073741824.0);
-      img[i] = (int32_t)fl;
+      n[i] = fl;
+      // the recorded image (pair keys only) saturates beyond 2^30
+      img[i] = (int32_t)fmin(fmax(fl, -1073741824.0), 1073741824.0);
       int32_t ai = (int32_t)(f * g.nc[i]);
       a[i] = ai < 0 ? 0 : (ai >= g.nc[i] ? g.nc[i] - 1 : ai);
     }
     for (int i = 0; i < 3; ++i)
-      xw[i] = x[i] - (g.B[3 * i] * img[0] + g.B[3 * i + 1] * img[1] + g.B[3 * i + 2] * img[2]);
+      xw[i] = x[i] - (g.B[3 * i] * n[0] + g.B[3 * i + 1] * n[1] + g.B[3 * i + 2] * n[2]);
   } else {
     // rotate (x' = Q^T x), then the rectangular rearrangement: reduce z by
     // r_z, then y by r_y, then x by r_x; the result lies in
     // [0,r11) x [0,r22) x [0,r33), a fundamental domain of the lattice.
     double y[3];
     for (int i = 0; i < 3; ++i) y[i] = g.Finv[3 * i] * x[0] + g.Finv[3 * i + 1] * x[1] + g.Finv[3 * i + 2] * x[2];
-    double k = floor(y[2] / g.B[8]);
-    k = fmin(fmax(k, -1073741824.0), 1073741824.0);
+    const double k = floor(y[2] / g.B[8]);
     y[0] -= k * g.B[2];
     y[1] -= k * g.B[5];
     y[2] -= k * g.B[8];
-    double j = floor(y[1] / g.B[4]);
-    j = fmin(fmax(j, -1073741824.0), 1073741824.0);
+    const double j = floor(y[1] / g.B[4]);
     y[0] -= j * g.B[1];
     y[1] -= j * g.B[4];
-    double i = floor(y[0] / g.B[0]);
-    i = fmin(fmax(i, -1073741824.0), 1073741824.0);
+    const double i = floor(y[0] / g.B[0]);
     y[0] -= i * g.B[0];
-    img[0] = (int32_t)i;
-    img[1] = (int32_t)j;
-    img[2] = (int32_t)k;
+    // the recorded image (pair keys only) saturates beyond 2^30
+    img[0] = (int32_t)fmin(fmax(i, -1073741824.0), 1073741824.0);
+    img[1] = (int32_t)fmin(fmax(j, -1073741824.0), 1073741824.0);
+    img[2] = (int32_t)fmin(fmax(k, -1073741824.0), 1073741824.0);
     for (int d = 0; d < 3; ++d) {
       int32_t ad = (int32_t)floor(y[d] / g.w[d]);
       a[d] = ad < 0 ? 0 : (ad >= g.nc[d] ? g.nc[d] - 1 : ad);
