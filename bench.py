@@ -46,13 +46,18 @@ OPS_PER_PAIR = 22
 # offset (16), the FP64 position for the exact re-evaluations is not counted,
 # perm (4), write F (12 in FP32) and cell_start (~4 per particle)
 SWEEP_BYTES_PER_PARTICLE = 16 + 4 + 12 + 4
+# algorithmic HBM bytes per particle of the cell build (bin pass): bin count
+# (read x 24, write cell and rank 8, count atomic 8), scatter (read cell,
+# rank, cell start 12, write perm 4), per-cell sort of perm (8), gather (read
+# perm 4 and x 24, write FP64 position 32, FP32 offset 16 and residual 16)
+BUILD_BYTES_PER_PARTICLE = 40 + 16 + 8 + 92
 
 # HBM traffic of the sweep kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes over this benchmark (default arguments, 3 steps), each
 # scaled by the reading of the same counter for a plain 1 GiB elementwise
 # kernel in the same run; see profiles/sweep_particle_do_lj1M_traffic.md.
 # Valid only while the sweep sources hash to src_sha (null otherwise).
-SWEEP_TRAFFIC = {"bytes_per_launch": 115504656, "src_sha": "8e167b4c610d53fc"}
+SWEEP_TRAFFIC = {"bytes_per_launch": 116558036, "src_sha": "ef010e974197c2db"}
 SWEEP_SOURCES = ["paper_1412_3784_amd/csrc/sweep_common.hpp", "paper_1412_3784_amd/csrc/kernels.hip",
                  "paper_1412_3784_amd/csrc/kernels.hpp", "paper_1412_3784_amd/csrc/geometry.hpp"]
 
@@ -190,6 +195,10 @@ def run_plain(a, out):
                    "density": 0.8, "rc": 2.5},
         "breakdown_ms": {"build": 1e3 * t_build / a.steps, "force": 1e3 * t_force / a.steps},
         "schedule": sched,
+        "bin_pass": {"bound": "hbm", "bytes_per_particle": BUILD_BYTES_PER_PARTICLE,
+                     "achieved_GBs": BUILD_BYTES_PER_PARTICLE * n / (t_build / a.steps) / 1e9,
+                     "peak_GBs": HBM_PEAK_GBS,
+                     "frac": BUILD_BYTES_PER_PARTICLE * n / (t_build / a.steps) / 1e9 / HBM_PEAK_GBS},
         "candidates_per_particle": tot_cands / (a.steps * n),
         "search_efficiency": 2 * tot_pairs / tot_cands,
         "roofline": roofline_alu(tot_cands, tot_pairs, t_force, a.steps,
