@@ -174,6 +174,51 @@ int orc_lattice_at(const double *L0, const double *A, double t, double *L)
  * matrix Mtot = prod_k M_k^{-p_k} satisfies Lred = L_t Mtot.
  * naut = 0: no remap (Lred = L_t).  Returns 0, -1 (bad automorphism),
  * -2 (flow not diagonal / not in the span of the log-eigenvalues).        */
+/* Sec. 2.2, planar shear (Lees-Edwards): for the shear flow A (A^2 = 0) the
+ * lattice is L_t = (I + tA) L0, and the automorphism M = I - N with N^2 = 0
+ * resets it.  In lattice coordinates L0^-1 A L0 = s N for a scalar s, so
+ * L_t M^p = L0 (I + (s t - p) N); applying M each time the box has been
+ * sheared by half a lattice spacing means p = floor(s t + 1/2) (the reset the
+ * paper recommends, bounding the deformation angle by 90 - atan 2 degrees).
+ * Mtot = M^p = I - p N.  Returns 0, -1 (bad automorphism) or -2 (A is not a
+ * shear of the lattice along N).                                          */
+static int reduce_shear(const double *L0, const double *A, double t, const int32_t *aut, double *Lred,
+                        int32_t *Mtot, int32_t *coef)
+{
+    int64_t M[9], N[9], NN[9], tmp[9];
+    for (int q = 0; q < 9; ++q) M[q] = aut[q];
+    if (iinv3(M, tmp)) return -1;
+    for (int q = 0; q < 9; ++q) N[q] = (q % 4 == 0 ? 1 : 0) - M[q];
+    imm3(N, N, NN);
+    for (int q = 0; q < 9; ++q)
+        if (NN[q] != 0) return -1;
+    double L0i[9], X[9];
+    if (inv3(L0, L0i)) return -1;
+    mm3(L0i, A, X);
+    mm3(X, L0, X);
+    double xn = 0.0, nn = 0.0, xmax = 0.0;
+    for (int q = 0; q < 9; ++q) {
+        xn += X[q] * (double)N[q];
+        nn += (double)(N[q] * N[q]);
+        xmax = fmax(xmax, fabs(X[q]));
+    }
+    if (nn == 0.0) return -1;
+    double sr = xn / nn;
+    for (int q = 0; q < 9; ++q)
+        if (fabs(X[q] - sr * (double)N[q]) > 1e-9 * (xmax + 1e-300)) return -2;
+    int64_t p = (int64_t)floor(sr * t + 0.5);
+    int64_t P[9];
+    for (int q = 0; q < 9; ++q) P[q] = (q % 4 == 0 ? 1 : 0) - p * N[q];
+    double Lt[9], Pd[9];
+    orc_lattice_at(L0, A, t, Lt);
+    for (int q = 0; q < 9; ++q) Pd[q] = (double)P[q];
+    mm3(Lt, Pd, Lred);
+    if (Mtot)
+        for (int q = 0; q < 9; ++q) Mtot[q] = (int32_t)P[q];
+    if (coef) coef[0] = (int32_t)p;
+    return 0;
+}
+
 int orc_reduce(const double *L0, const double *A, double t, int naut, const int32_t *aut,
                double *Lred, int32_t *Mtot, int32_t *coef)
 {
@@ -186,7 +231,7 @@ int orc_reduce(const double *L0, const double *A, double t, int naut, const int3
     if (naut < 0 || naut > 2) return -1;
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
-            if (r != c && A[3 * r + c] != 0.0) return -2;
+            if (r != c && A[3 * r + c] != 0.0) return naut == 1 ? reduce_shear(L0, A, t, aut, Lred, Mtot, coef) : -2;
     double L0i[9];
     if (inv3(L0, L0i)) return -1;
     double mu[2][3];

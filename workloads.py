@@ -59,12 +59,19 @@ KR_LAMBDA = (3.0 + math.sqrt(5.0)) / 2.0
 # unimodular matrices with independent log-eigenvalue vectors.
 GKR_M1 = np.array([[1, -1, 0], [-1, 2, -1], [0, -1, 2]], dtype=np.int32)
 GKR_M2 = ((GKR_M1 - np.eye(3, dtype=np.int32)) @ (GKR_M1 - np.eye(3, dtype=np.int32))).astype(np.int32)
+# Lees-Edwards automorphism of planar shear (Sec. 2.2)
+LE_M = np.array([[1, -1, 0], [0, 1, 0], [0, 0, 1]], dtype=np.int32)
 
 FLOWS = ("planar", "uniaxial", "biaxial")
 
 
 def flow_matrix(kind: str, rate: float) -> np.ndarray:
-    """Diagonal, traceless velocity-gradient matrix A of the background flow u = A x."""
+    """Traceless velocity-gradient matrix A of the background flow u = A x:
+    diagonal for the elongational flows, A[0][1] = rate for planar shear."""
+    if kind == "shear":
+        A = np.zeros((3, 3))
+        A[0, 1] = rate
+        return A
     d = {"planar": (1.0, -1.0, 0.0),
          "uniaxial": (1.0, -0.5, -0.5),
          "biaxial": (0.5, 0.5, -1.0),
@@ -102,6 +109,8 @@ def nominal_period(kind: str, rate: float) -> float:
     automorphism eigenvalue divided by the rate."""
     if kind == "planar":
         return math.log(KR_LAMBDA) / rate
+    if kind == "shear":
+        return 1.0 / rate
     lam1 = float(np.max(np.linalg.eigvalsh(GKR_M1.astype(np.float64))))
     return math.log(lam1) / rate
 
@@ -155,9 +164,10 @@ def make_box(flow: str, rate: float, n: int, *, density: Optional[float] = None,
              grid: Optional[int] = None, jitter_sigma: float = 0.0) -> Box:
     """A box of n particles with initial side `side` (or (n/density)^(1/3)).
 
-    flow in {"planar", "uniaxial", "biaxial", "none"}; planar uses the KR
-    basis and automorphism, uniaxial/biaxial the generalised-KR pair, "none"
-    an axis-aligned cube with no remapping.  The strain time is `t`, or
+    flow in {"planar", "uniaxial", "biaxial", "shear", "none"}; planar uses
+    the KR basis and automorphism, uniaxial/biaxial the generalised-KR pair,
+    shear an axis-aligned cube with the Lees-Edwards automorphism, "none" an
+    axis-aligned cube with no remapping.  The strain time is `t`, or
     `t_frac` times the nominal period.  Positions are uniform fractional
     coordinates, or a grid of grid^3 sites at (i+1/2)/grid plus Gaussian
     Cartesian jitter.
@@ -184,6 +194,9 @@ def make_box(flow: str, rate: float, n: int, *, density: Optional[float] = None,
     elif flow in ("uniaxial", "biaxial"):
         L0 = gkr_initial_basis(side)
         auts = [GKR_M1.copy(), GKR_M2.copy()]
+    elif flow == "shear":
+        L0 = np.eye(3) * side
+        auts = [LE_M.copy()]
     else:
         L0 = np.eye(3) * side
         auts = []
