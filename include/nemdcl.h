@@ -117,14 +117,20 @@ int ncl_set_potential(ncl_handle h, double eps, double sigma, double rc, int shi
 int ncl_set_option(ncl_handle h, int option, double value);
 
 /* Lattice at strain time t (host pointers).  L_t = exp(tA) L0 (Sec. 2.1).
+ * A is either diagonal (elongational flows) or a planar shear with A^2 = 0
+ * (Sec. 2.2), for which L_t = (I + tA) L0; other flows return NCL_E_LATTICE.
  * naut = 0: no remap, the basis is L_t.
- * naut = 1 (Kraynik-Reinelt, eq:kr) or 2 (generalised KR, Sec. 2.2):
- * `aut` holds M1 (and M2) as int32[9] row-major, each of determinant 1 and
- * such that L0 M_k L0^-1 is diagonal with positive entries exp(mu_k); A must
- * be diagonal with t diag(A) in the span of the mu_k.  The stretch
+ * Diagonal A, naut = 1 (Kraynik-Reinelt, eq:kr) or 2 (generalised KR,
+ * Sec. 2.2): `aut` holds M1 (and M2) as int32[9] row-major, each of
+ * determinant 1 and such that L0 M_k L0^-1 is diagonal with positive entries
+ * exp(mu_k); t diag(A) must lie in the span of the mu_k.  The stretch
  * t diag(A) = sum_k alpha_k mu_k is reduced to eps = t diag(A) -
  * sum_k p_k mu_k with p_k = floor(alpha_k + 1/2), and the basis used is
- * Lred = exp(diag(eps)) L0 = L_t M1^-p1 M2^-p2.  Host-side FP64; no GPU work. */
+ * Lred = exp(diag(eps)) L0 = L_t M1^-p1 M2^-p2.
+ * Shear A, naut = 1 (Lees-Edwards, eq:Mshear): M = I - N with N^2 = 0 and
+ * L0^-1 A L0 = s N; M is applied each time the box has been sheared by half
+ * a lattice spacing: Lred = L_t M^p = L0 (I + (s t - p) N), p = floor(s t +
+ * 1/2).  Host-side FP64; no GPU work. */
 int ncl_set_lattice(ncl_handle h, const double L0[9], const double A[9], double t, int naut,
                     const int32_t *aut);
 

@@ -78,28 +78,84 @@ NCL_HD int idiv_floor32(int a, int b) {  // b > 0
 // vectors mu_k of L0 M_k L0^-1 (diagonal by construction of L0, eq:kr), the
 // Gram matrix of the mu_k, and the automorphisms and their inverses.
 struct RemapPolicy {
-  int naut;            // 0, 1 (KR) or 2 (generalised KR)
+  int naut;            // 0, 1 (KR / Lees-Edwards) or 2 (generalised KR)
+  int shear;           // 1: planar shear, A^2 = 0 (Sec. 2.2, Lees-Edwards)
   double L0[9];
   double adiag[3];     // diagonal of A
   double mu[2][3];
   double gram_inv[4];  // inverse of the 2x2 (or 1x1) Gram matrix of the mu_k
   int64_t M[2][9];
   int64_t Minv[2][9];
+  // shear: L_t = L0 (I + s t N), N = I - M (N^2 = 0), L0N = L0 N; without an
+  // automorphism N is replaced by X = L0^-1 A L0 itself (s = 1)
+  double s;
+  double L0N[9];
+  int64_t N[9];
 };
 
 enum { GEOM_OK = 0, GEOM_E_AUT = -1, GEOM_E_FLOW = -2, GEOM_E_SMALL = -3, GEOM_E_SINGULAR = -4 };
 
 // host-only set-up; returns GEOM_* code
+// Planar shear (Sec. 2.2): A nilpotent (A^2 = 0), L_t = (I + tA) L0.  With
+// the automorphism M, N = I - M must satisfy N^2 = 0 and L0^-1 A L0 = s N;
+// the reset M^p, p = floor(s t + 1/2), is applied whenever the box has been
+// sheared by half a lattice spacing, so Lred = L0 (I + (s t - p) N) and
+// Mtot = M^p = I - p N.
+inline int shear_policy_init(RemapPolicy* p, const double* A, int naut, const int32_t* aut) {
+  double AA[9], amax = 0.0;
+  mat_mul(A, A, AA);
+  for (int k = 0; k < 9; ++k) amax = fmax(amax, fabs(A[k]));
+  for (int k = 0; k < 9; ++k)
+    if (fabs(AA[k]) > 1e-12 * amax * amax) return GEOM_E_FLOW;
+  double L0i[9], X[9];
+  if (!mat_inv(p->L0, L0i)) return GEOM_E_SINGULAR;
+  mat_mul(L0i, A, X);
+  mat_mul(X, p->L0, X);
+  p->shear = 1;
+  if (naut == 0) {
+    // no reset: L_t = L0 (I + t X)
+    p->s = 1.0;
+    mat_mul(p->L0, X, p->L0N);
+    for (int k = 0; k < 9; ++k) p->N[k] = 0;
+    return GEOM_OK;
+  }
+  if (naut != 1) return GEOM_E_FLOW;
+  int64_t M[9], NN[9];
+  for (int k = 0; k < 9; ++k) M[k] = aut[k];
+  if (imat_det(M) != 1) return GEOM_E_AUT;
+  for (int k = 0; k < 9; ++k) p->N[k] = (k % 4 == 0 ? 1 : 0) - M[k];
+  imat_mul(p->N, p->N, NN);
+  for (int k = 0; k < 9; ++k)
+    if (NN[k] != 0) return GEOM_E_AUT;
+  double xn = 0.0, nn = 0.0, xmax = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    xn += X[k] * (double)p->N[k];
+    nn += (double)(p->N[k] * p->N[k]);
+    xmax = fmax(xmax, fabs(X[k]));
+  }
+  if (nn == 0.0) return GEOM_E_AUT;
+  p->s = xn / nn;
+  for (int k = 0; k < 9; ++k)
+    if (fabs(X[k] - p->s * (double)p->N[k]) > 1e-9 * (xmax + 1e-300)) return GEOM_E_FLOW;
+  double Nd[9];
+  for (int k = 0; k < 9; ++k) Nd[k] = (double)p->N[k];
+  mat_mul(p->L0, Nd, p->L0N);
+  return GEOM_OK;
+}
+
 inline int remap_policy_init(RemapPolicy* p, const double* L0, const double* A, int naut,
                              const int32_t* aut) {
   for (int k = 0; k < 9; ++k) p->L0[k] = L0[k];
   p->naut = naut;
+  p->shear = 0;
   for (int k = 0; k < 3; ++k) p->adiag[k] = A[4 * k];
   if (naut < 0 || naut > 2) return GEOM_E_AUT;
-  if (naut == 0) return GEOM_OK;
+  bool diag = true;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
-      if (i != j && A[3 * i + j] != 0.0) return GEOM_E_FLOW;
+      if (i != j && A[3 * i + j] != 0.0) diag = false;
+  if (!diag) return shear_policy_init(p, A, naut, aut);
+  if (naut == 0) return GEOM_OK;
   double L0i[9];
   if (!mat_inv(L0, L0i)) return GEOM_E_SINGULAR;
   for (int a = 0; a < naut; ++a) {
@@ -173,6 +229,14 @@ inline int remap_policy_init(RemapPolicy* p, const double* L0, const double* A, 
 NCL_HD void remap_at(const RemapPolicy& p, double t, double* Lred, int64_t* coef) {
   double th[3] = {t * p.adiag[0], t * p.adiag[1], t * p.adiag[2]};
   coef[0] = coef[1] = 0;
+  if (p.shear) {
+    // Lred = L0 + (s t - p) L0 N
+    const double st = p.s * t;
+    if (p.naut == 1) coef[0] = (int64_t)floor(st + 0.5);
+    const double f = st - (double)coef[0];
+    for (int k = 0; k < 9; ++k) Lred[k] = p.L0[k] + f * p.L0N[k];
+    return;
+  }
   if (p.naut >= 1) {
     double b0 = 0, b1 = 0;
     for (int i = 0; i < 3; ++i) {
@@ -199,8 +263,13 @@ NCL_HD void remap_at(const RemapPolicy& p, double t, double* Lred, int64_t* coef
   }
 }
 
-// Mtot = M1^-p1 M2^-p2, so that Lred = L_t Mtot
+// Mtot = M1^-p1 M2^-p2 (elongation) or M^p (shear), so that Lred = L_t Mtot
 NCL_HD void remap_matrix(const RemapPolicy& p, const int64_t* coef, int64_t* Mtot) {
+  if (p.shear) {
+    // M^p = I - p N
+    for (int k = 0; k < 9; ++k) Mtot[k] = (k % 4 == 0 ? 1 : 0) - coef[0] * p.N[k];
+    return;
+  }
   int64_t R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   for (int a = 0; a < p.naut; ++a) {
     const int64_t* step = coef[a] > 0 ? p.Minv[a] : p.M[a];

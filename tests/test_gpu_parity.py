@@ -201,3 +201,27 @@ def test_autotuned_sweep_matches_oracle(variant):
     assert h.stats()["tune_ms"] == st["tune_ms"] and h.stats()["sweep"] == st["sweep"]
     assert (g1["F"] == g2["F"]).all()
     h.close()
+
+
+@pytest.mark.parametrize("variant", VARS)
+@pytest.mark.parametrize("prec", PRECS)
+def test_shear_lees_edwards_across_resets(variant, prec):
+    """Planar shear with Lees-Edwards resets (Sec. 2.2): strains on both sides
+    of the first two resets, up to the largest deformation angle."""
+    for tf in (0.2, 0.49, 0.51, 1.0, 1.49, 1.51):
+        box = wl.make_box("shear", 0.5, 3000, density=0.8442, pot=wl.WCA, t_frac=tf, seed=61)
+        x = oracle_positions(box)
+        r = run_oracle(box, x)
+        for sweep in SWEEPS:
+            g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
+            compare(g, r, prec, label=f"shear/{tf}/{variant}/{prec}/sweep{sweep}")
+
+
+def test_shear_lj_large_box():
+    box = wl.make_box("shear", 0.3, 65536, density=0.8, pot=wl.LJ25, t_frac=1.47, seed=62)
+    x = oracle_positions(box)
+    r = run_oracle(box, x)
+    for variant in VARS:
+        g = run_gpu(box, x, variant, "fp32")
+        compare(g, r, "fp32", label=f"shear-lj/{variant}")
+

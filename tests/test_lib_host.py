@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol(ncl):
     assert sorted(ncl.EXPORTED) == syms
 
 
-@pytest.mark.parametrize("flow", ["planar", "uniaxial", "biaxial", "none"])
+@pytest.mark.parametrize("flow", ["planar", "uniaxial", "biaxial", "shear", "none"])
 def test_reduced_lattice_matches_oracle(ncl, orc, flow):
     box = wl.make_box(flow, 0.37, 100, side=12.0)
     h = ncl.ncl_create(0, 0)
@@ -102,3 +102,28 @@ def test_error_codes(ncl):
     finally:
         ncl.ncl_destroy(h)
     assert ncl._lib.ncl_destroy(None) == ncl.NCL_E_ARG
+
+
+def test_shear_without_reset_and_rejected_flows(ncl):
+    """A shear flow without automorphism is the plain L_t = (I + tA) L0; a
+    non-diagonal flow that is not a shear of the lattice is rejected."""
+    box = wl.make_box("shear", 0.4, 10, side=5.0, t=0.0)
+    h = ncl.ncl_create(0, 0)
+    try:
+        ncl.ncl_set_lattice(h, box.L0, box.A, 2.5, [])
+        L, M, c = ncl.ncl_get_lattice(h)
+        assert np.allclose(L, (np.eye(3) + 2.5 * box.A) @ box.L0, rtol=0, atol=1e-13)
+        assert (M == np.eye(3)).all()
+        A = box.A.copy()
+        A[1, 0] = 0.3  # A^2 != 0
+        with pytest.raises(ncl.NclError) as e:
+            ncl.ncl_set_lattice(h, box.L0, A, 1.0, box.automorphisms)
+        assert e.value.code == ncl.NCL_E_LATTICE
+        A = np.zeros((3, 3))
+        A[0, 2] = 0.3  # nilpotent, but not along the automorphism's N
+        with pytest.raises(ncl.NclError) as e:
+            ncl.ncl_set_lattice(h, box.L0, A, 1.0, box.automorphisms)
+        assert e.value.code == ncl.NCL_E_LATTICE
+    finally:
+        ncl.ncl_destroy(h)
+
