@@ -79,7 +79,9 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 20)
     p.add_argument("--variant", default="do", choices=["do", "ds"])
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp32k", "fp64"])
-    p.add_argument("--sweep", default="auto", choices=["tiled", "particle", "auto"])
+    p.add_argument("--sweep", default="auto", choices=["tiled", "particle", "auto", "half"])
+    p.add_argument("--deterministic", type=int, default=1, choices=[0, 1],
+                   help="0: the autotuner may pick the half list (atomic sums)")
     p.add_argument("--replicas", type=int, default=None, help="batch/nemd: number of replicas")
     p.add_argument("--no-batch", action="store_true", help="plain: skip the batched comparison")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -131,7 +133,8 @@ def run_plain(a, out):
     h = Handle(0, stream)
     h.set_potential(b0.pot)
     h.set_option(ncl.NCL_OPT_SWEEP, {"tiled": ncl.NCL_SWEEP_TILED, "particle": ncl.NCL_SWEEP_PARTICLE,
-                                     "auto": ncl.NCL_SWEEP_AUTO}[a.sweep])
+                                     "auto": ncl.NCL_SWEEP_AUTO, "half": ncl.NCL_SWEEP_HALF}[a.sweep])
+    h.set_option(ncl.NCL_OPT_DETERMINISTIC, a.deterministic)
     # positions for every strain value: the fixed fractional configuration
     # carried by the flow, x_k = L(t_k) s, resident in HBM before timing
     s = torch.from_numpy(b0.frac).to(dev)
@@ -159,13 +162,13 @@ def run_plain(a, out):
 
     # pair and candidate counts per strain value (untimed; the autotuner
     # settles the schedule of every strain's workload class here)
-    pairs, cands = np.zeros(64), np.zeros(64)
+    pairs, cands, halfk = np.zeros(64), np.zeros(64), np.zeros(64, dtype=bool)
     sched = {}
     for k in range(64):
         step(k)
         st = h.stats()
-        pairs[k], cands[k] = st["pairs"] / 2, st["candidates"]
-        key = ("tiled" + "x".join(map(str, st["brick"]))) if st["sweep"] == 0 else "particle"
+        pairs[k], cands[k], halfk[k] = st["pairs"] / 2, st["candidates"], st["sweep"] == ncl.NCL_SWEEP_HALF
+        key = {0: "tiled" + "x".join(map(str, st["brick"])), 1: "particle", 3: "half"}[st["sweep"]]
         sched[key] = sched.get(key, 0) + 1
     for k in range(a.warmup):
         step(k)
@@ -181,6 +184,8 @@ def run_plain(a, out):
     ks = [k % 64 for k in range(a.steps)]
     tot_pairs = float(sum(pairs[k] for k in ks))
     tot_cands = float(sum(cands[k] for k in ks))
+    # pair evaluations: twice per interacting pair for full lists, once for the half list
+    tot_evals = float(sum(pairs[k] * (1 if halfk[k] else 2) for k in ks))
     out.update({
         "metric": "pair interactions/s (bin + force, FP32 offsets, 1e-5 force accuracy)",
         "value": tot_pairs / wall,
@@ -200,8 +205,9 @@ def run_plain(a, out):
                      "peak_GBs": HBM_PEAK_GBS,
                      "frac": BUILD_BYTES_PER_PARTICLE * n / (t_build / a.steps) / 1e9 / HBM_PEAK_GBS},
         "candidates_per_particle": tot_cands / (a.steps * n),
-        "search_efficiency": 2 * tot_pairs / tot_cands,
-        "roofline": roofline_alu(tot_cands, tot_pairs, t_force, a.steps,
+        "search_efficiency": tot_evals / tot_cands,
+        "deterministic": bool(a.deterministic) and a.sweep != "half",
+        "roofline": roofline_alu(tot_cands, tot_evals / 2, t_force, a.steps,
                                  f"sweep[{a.sweep}]<{a.variant},{a.precision}>", n),
     })
     h.close()

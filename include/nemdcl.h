@@ -78,8 +78,19 @@ extern "C" {
                                     workload class (variant, precision, cells per
                                     axis, occupancy) times the per-particle sweep
                                     and the tiled sweep with its three best-ranked
-                                    bricks on the handle's stream, synchronising
-                                    once, and keeps the fastest                   */
+                                    bricks (and, when NCL_OPT_DETERMINISTIC is 0,
+                                    the half list) on the handle's stream,
+                                    synchronising once, and keeps the fastest;
+                                    3 = half list: each pair evaluated once and
+                                    applied to both particles with atomic sums
+                                    (NCL_PREC_FP32 only; forces are then not
+                                    bit-identical from run to run)               */
+#define NCL_OPT_DETERMINISTIC 4  /* 1 (default): the autotuner only picks
+                                    schedules whose forces are bit-identical from
+                                    run to run; 0: it may pick the half list.
+                                    Set sweep options before ncl_build_cells,
+                                    which sizes the half list's FP64 force array
+                                    (24 bytes per particle)                       */
 
 typedef struct ncl_ctx *ncl_handle;
 
@@ -90,15 +101,18 @@ typedef struct {
     int32_t cells[3];       /* c_i (Sec. 4.1) or l_i (Sec. 4.2)                   */
     int32_t max_occupancy;  /* most particles in one cell                         */
     int64_t ncells;
-    int64_t candidates;     /* distance checks, each ordered (i, j-image) once    */
+    int64_t candidates;     /* distance checks, each ordered (i, j-image) once
+                               (half list: each unordered pair once)           */
     int64_t pairs;          /* in-range ordered pairs: twice the interacting set  */
-    int64_t fp64_pairs;     /* FP32 modes: pairs re-evaluated in FP64             */
+    int64_t fp64_pairs;     /* FP32 modes: pairs re-evaluated in FP64 (ordered;
+                               half list: unordered)                           */
     int64_t neighbourhood;  /* sum over particles of neighbourhood cells visited   */
-    int32_t sweep;          /* schedule of the last force pass: 0 tiled, 1 per particle */
+    int32_t sweep;          /* schedule of the last force pass: 0 tiled, 1 per
+                               particle, 3 half list                           */
     int32_t brick[3];       /* its brick of cells when tiled                      */
-    float tune_ms[4];       /* autotuner timings of this workload class: per
-                               particle, then tiled with the three best-ranked
-                               bricks (-1: not timed)                             */
+    float tune_ms[5];       /* autotuner timings of this workload class: per
+                               particle, tiled with the three best-ranked
+                               bricks, half list (-1: not timed)               */
 } ncl_stats;
 
 /* Create a handle on HIP device `device` that enqueues on `stream` (a

@@ -27,6 +27,7 @@ struct ncl_ctx {
   // options
   int do_tight = 1;
   int sweep_mode = SWEEP_AUTO;
+  int deterministic = 1;
   double close_r = 0.45, band = 1e-5;
   // lattice
   bool have_lattice = false;
@@ -61,13 +62,15 @@ struct ncl_ctx {
     uint64_t key;
     int mode;
     int brick[6];
-    float ms[4];
+    float ms[5];
   };
   std::vector<Tuned> tuned;
   Tuned last{};
   int used_mode = SWEEP_PARTICLE;  // schedule of the last force pass
   int used_brick[3] = {0, 0, 0};
   double* dbgF = nullptr;  // internal F/U/W for ncl_debug_pairs
+  double* facc = nullptr;  // half-list sweep: FP64 forces in slot order
+  size_t cap_facc = 0;
   // small device words: [0..3] stats (u64), then maxocc (u32), err (i32)
   unsigned long long* small = nullptr;
   std::string err;
@@ -129,8 +132,8 @@ int ncl_destroy(ncl_handle h) {
   int code = NCL_OK;
   if (h->small) {  // device state exists only after a build
     if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) code = NCL_E_HIP;
-    void* bufs[] = {h->cell_of, h->rank, h->count, h->cstart, h->perm,     h->scan_tmp, h->pos64,
-                    h->pos32,   h->pos32lo, h->wrap, h->partial, h->overflow, h->dbgF, h->small};
+    void* bufs[] = {h->cell_of, h->rank,    h->count, h->cstart,  h->perm,     h->scan_tmp, h->pos64, h->pos32,
+                    h->pos32lo, h->wrap,    h->partial, h->overflow, h->dbgF, h->facc,     h->small};
     for (void* b : bufs)
       if (b && hipFree(b) != hipSuccess) code = NCL_E_HIP;
   }
@@ -159,9 +162,13 @@ int ncl_set_option(ncl_handle h, int option, double value) {
       h->close_r = value;
       break;
     case NCL_OPT_SWEEP:
-      if (value != 0.0 && value != 1.0 && value != 2.0)
-        return fail(h, NCL_E_ARG, "sweep mode must be 0 (tiled), 1 (per particle) or 2 (autotuned)");
+      if (value != 0.0 && value != 1.0 && value != 2.0 && value != 3.0)
+        return fail(h, NCL_E_ARG, "sweep mode must be 0 (tiled), 1 (per particle), 2 (autotuned) or 3 (half list)");
       h->sweep_mode = (int)value;
+      break;
+    case NCL_OPT_DETERMINISTIC:
+      if (value != 0.0 && value != 1.0) return fail(h, NCL_E_ARG, "deterministic must be 0 or 1");
+      h->deterministic = (int)value;
       break;
     case NCL_OPT_BAND:
       if (!(value >= 0.0 && value < 0.1)) return fail(h, NCL_E_ARG, "band must be in [0, 0.1)");
@@ -381,12 +388,15 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
       h->partial = nullptr;
       h->cap_bricks = 0;
       HIPCHK(h, hipMalloc((void**)&h->overflow, (nbr + 2) * sizeof(uint32_t)));
-      HIPCHK(h, hipMalloc((void**)&h->partial, 8 * (nbr + 2) * sizeof(double)));
+      HIPCHK(h, hipMalloc((void**)&h->partial, PART_STRIDE * (nbr + 2) * sizeof(double)));
       h->cap_bricks = nbr + 2;
     }
   }
   const size_t nscan = ((size_t)nc + 2047) / 2048 + 1;
   HIPCHK(h, grow(&h->scan_tmp, &h->cap_scan, nscan));
+  if (precision == NCL_PREC_FP32 &&
+      (h->sweep_mode == SWEEP_HALF || (h->sweep_mode == SWEEP_AUTO && !h->deterministic)))
+    HIPCHK(h, grow(&h->facc, &h->cap_facc, 3 * un));
 
   h->geom = g;
   h->variant = variant;
@@ -486,6 +496,9 @@ static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
   A->overflow = h->overflow;
   brick_args(h, A);
   A->rclose2_64 = h->close_r * h->close_r * s2;
+  A->fix_q = ldexp(h->eps / h->sigma, -20);
+  A->fix_inv = 1.0 / A->fix_q;
+  A->rwin2_64 = fmax(A->rclose2_64, 0.09 * s2);
   A->p32.sig2 = (float)s2;
   A->p32.eps4 = (float)(4.0 * h->eps);
   A->p32.eps24 = (float)(24.0 * h->eps);
@@ -500,7 +513,7 @@ static uint64_t tune_key(const ncl_ctx* h) {
   const int ob = occ > 0.0 ? (int)floor(4.0 * log2(occ)) + 64 : 0;
   uint64_t k = (uint64_t)h->geom.variant | ((uint64_t)h->precision << 2) | ((uint64_t)(ob & 0xff) << 4);
   for (int a = 0; a < 3; ++a) k |= (uint64_t)(h->geom.nc[a] & 0xffff) << (12 + 16 * a);
-  return k;
+  return k | ((uint64_t)(h->deterministic & 1) << 60);
 }
 
 static hipError_t sweep_with(ncl_ctx* h, SweepArgs* A, int mode, const int* brick, void* F, double* U, double* W) {
@@ -514,13 +527,21 @@ static hipError_t sweep_with(ncl_ctx* h, SweepArgs* A, int mode, const int* bric
   L.debug = false;
   L.U = U;
   L.W = W;
+  L.facc = h->facc;
   return launch_sweep(L, h->stream);
+}
+
+// the half-list sweep runs in FP32 precision and needs its force array
+static bool half_ok(const ncl_ctx* h) {
+  return h->precision == NCL_PREC_FP32 && h->facc && h->cap_facc >= 3 * (size_t)h->n;
 }
 
 // Autotuner: time each candidate schedule once on the caller's stream (after
 // one untimed launch) with HIP events; the fastest is cached for the class.
+// The half list is a candidate only when run-to-run identical forces are not
+// required.
 static int autotune(ncl_ctx* h, SweepArgs* A, void* F, double* U, double* W, ncl_ctx::Tuned* out) {
-  int modes[4], bricks[4][6], nc = 0;
+  int modes[5], bricks[5][6], nc = 0;
   modes[nc] = SWEEP_PARTICLE;
   for (int k = 0; k < 6; ++k) bricks[nc][k] = h->cand[0][k];
   ++nc;
@@ -528,13 +549,18 @@ static int autotune(ncl_ctx* h, SweepArgs* A, void* F, double* U, double* W, ncl
     modes[nc] = SWEEP_TILED;
     for (int k = 0; k < 6; ++k) bricks[nc][k] = h->cand[r][k];
   }
+  if (!h->deterministic && half_ok(h)) {
+    modes[nc] = SWEEP_HALF;
+    for (int k = 0; k < 6; ++k) bricks[nc][k] = h->cand[0][k];
+    ++nc;
+  }
   hipEvent_t e0, e1;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
   int best = 0;
   float bms = 3.0e38f;
   out->key = tune_key(h);
-  for (int c = 0; c < 4; ++c) out->ms[c] = -1.0f;
+  for (int c = 0; c < 5; ++c) out->ms[c] = -1.0f;
   for (int c = 0; c < nc; ++c) {
     hipError_t e = sweep_with(h, A, modes[c], bricks[c], F, U, W);
     if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
@@ -548,7 +574,7 @@ static int autotune(ncl_ctx* h, SweepArgs* A, void* F, double* U, double* W, ncl
       (void)hipEventDestroy(e1);
       return hip_fail(h, e, "autotune");
     }
-    out->ms[c] = ms;
+    out->ms[modes[c] == SWEEP_HALF ? 4 : c] = ms;
     if (ms < bms) {
       bms = ms;
       best = c;
@@ -569,6 +595,8 @@ int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
   SweepArgs A;
   fill_sweep_args(h, &A, F);
   int mode = h->sweep_mode;
+  if (mode == SWEEP_HALF && !half_ok(h))
+    return fail(h, NCL_E_ARG, "the half-list sweep needs NCL_PREC_FP32 (set the sweep option before ncl_build_cells)");
   int brick[6];
   for (int k = 0; k < 6; ++k) brick[k] = h->cand[0][k];
   if (mode == SWEEP_AUTO) {
@@ -617,6 +645,8 @@ int ncl_debug_pairs(ncl_handle h, int64_t* count, uint64_t* hash) {
   L.debug = true;
   L.U = h->dbgF + 3 * (size_t)h->n;
   L.W = h->dbgF + 3 * (size_t)h->n + 1;
+  L.facc = h->facc;
+  if (L.mode == SWEEP_HALF && !half_ok(h)) return fail(h, NCL_E_ARG, "the half-list sweep needs NCL_PREC_FP32");
   hipError_t e = launch_sweep(L, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "debug sweep launch");
   return NCL_OK;
@@ -642,10 +672,10 @@ int ncl_get_stats(ncl_handle h, ncl_stats* out) {
   out->max_occupancy = (int32_t)(uint32_t)(w[4] & 0xffffffffull);
   out->sweep = h->used_mode;
   for (int k = 0; k < 3; ++k) out->brick[k] = h->used_brick[k];
-  for (int k = 0; k < 4; ++k) out->tune_ms[k] = -1.0f;
+  for (int k = 0; k < 5; ++k) out->tune_ms[k] = -1.0f;
   for (const auto& t : h->tuned)
     if (t.key == tune_key(h))
-      for (int k = 0; k < 4; ++k) out->tune_ms[k] = t.ms[k];
+      for (int k = 0; k < 5; ++k) out->tune_ms[k] = t.ms[k];
   const int errw = (int)(uint32_t)(w[5] & 0xffffffffull);
   if (errw) {
     int zero = 0;

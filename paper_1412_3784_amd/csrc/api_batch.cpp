@@ -123,6 +123,7 @@ static void sweep_args(ncl_batch* b, SweepArgs* A, void* F) {
   A->n = (uint32_t)b->nslots;
   A->rc2 = rc2;
   A->rclose2_64 = b->close_r * b->close_r * s2;
+  A->fix_q = A->fix_inv = A->rwin2_64 = 0.0;  // half list: single-box only
   A->rclose2 = (float)A->rclose2_64;
   A->p64.sig2 = s2;
   A->p64.eps4 = 4.0 * b->eps;
@@ -184,7 +185,7 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->cell_of, tot);
   if (e == hipSuccess) e = dalloc(&b->rank, tot);
   if (e == hipSuccess) e = dalloc(&b->rep, tot);
-  if (e == hipSuccess) e = dalloc(&b->partial, 8 * (slots / 256 + 1));
+  if (e == hipSuccess) e = dalloc(&b->partial, PART_STRIDE * (slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->kpart, 3 * (slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->pol, nrep);
   if (e == hipSuccess) e = dalloc(&b->t0_d, nrep);

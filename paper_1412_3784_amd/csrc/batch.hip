@@ -96,22 +96,25 @@ __global__ void kb_scatter(BatchDev D) {
 
 __global__ void kb_cell_sort(BatchDev D) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.ncells) return;
-  if (D.err[0] & 1) return;  // non-finite input: cells may be huge, skip the sort
-  const uint32_t r = find_rep(D.cell_off, D.nrep, c);
-  const uint32_t pad = D.slot_off[r] - D.n_off[r];
-  const uint32_t b = D.cstart[c] + pad, e = D.cstart[c + 1] + pad;
-  uint32_t* perm = D.perm;
-  for (uint32_t k = b + 1; k < e; ++k) {
-    const uint32_t v = perm[k];
-    uint32_t q = k;
-    while (q > b && perm[q - 1] > v) {
-      perm[q] = perm[q - 1];
-      --q;
+  uint32_t occ = 0;
+  // (non-finite input: cells may be huge, the sort is skipped)
+  if (c < D.ncells && !(D.err[0] & 1)) {
+    const uint32_t r = find_rep(D.cell_off, D.nrep, c);
+    const uint32_t pad = D.slot_off[r] - D.n_off[r];
+    const uint32_t b = D.cstart[c] + pad, e = D.cstart[c + 1] + pad;
+    uint32_t* perm = D.perm;
+    for (uint32_t k = b + 1; k < e; ++k) {
+      const uint32_t v = perm[k];
+      uint32_t q = k;
+      while (q > b && perm[q - 1] > v) {
+        perm[q] = perm[q - 1];
+        --q;
+      }
+      perm[q] = v;
     }
-    perm[q] = v;
+    occ = e - b;
   }
-  atomicMax(D.maxocc, e - b);
+  wave_atomic_max(D.maxocc, occ);
 }
 
 __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
@@ -173,19 +176,24 @@ __global__ void __launch_bounds__(SW_THREADS) kb_sweep(SweepArgs A0, BatchDev D)
 // per replica: U = 1/2 sum u, W = 1/2 sum w over its workgroups, in order;
 // DO rotates W back to Cartesian
 __global__ void kb_finalize(BatchDev D, const double* __restrict__ partial, double* __restrict__ U,
-                            double* __restrict__ W) {
-  __shared__ double red[4][8];
+                            double* __restrict__ W, unsigned long long* __restrict__ stats) {
+  __shared__ double red[4][PART_STRIDE];
   const uint32_t r = blockIdx.x;
   const uint32_t b0 = D.slot_off[r] / SW_THREADS, b1 = D.slot_off[r + 1] / SW_THREADS;
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  double v[PART_STRIDE] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (uint32_t b = b0 + threadIdx.x; b < b1; b += blockDim.x)
-    for (int k = 0; k < 7; ++k) v[k] += partial[8 * (size_t)b + k];
+    for (int k = 0; k < PART_STRIDE; ++k)
+      if (k != 7) v[k] += partial[PART_STRIDE * (size_t)b + k];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < PART_STRIDE; ++k) {
     const double t = warp_sum(v[k]);
     if (lane == 0) red[wid][k] = t;
   }
   __syncthreads();
+  if (threadIdx.x < 4) {  // one addition per replica and counter (statistics are exact in FP64)
+    const double c = ((red[0][8 + threadIdx.x] + red[1][8 + threadIdx.x]) + red[2][8 + threadIdx.x]) + red[3][8 + threadIdx.x];
+    if (c != 0.0) atomicAdd(&stats[threadIdx.x], (unsigned long long)c);
+  }
   if (threadIdx.x == 0) {
     double s[7];
     for (int k = 0; k < 7; ++k) s[k] = 0.5 * (((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]);
@@ -362,7 +370,7 @@ hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, boo
     NCL_BSW(VAR_DO, 0) NCL_BSW(VAR_DO, 1) NCL_BSW(VAR_DO, 2)
 #undef NCL_BSW
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W);
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats);
   return hipGetLastError();
 }
 

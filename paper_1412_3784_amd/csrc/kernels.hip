@@ -116,18 +116,21 @@ __global__ void k_scatter(const uint32_t* __restrict__ cell_of, const uint32_t* 
 __global__ void k_cell_sort(const uint32_t* __restrict__ cstart, uint32_t ncells, uint32_t* __restrict__ perm,
                             uint32_t* __restrict__ maxocc) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncells) return;
-  const uint32_t b = cstart[c], e = cstart[c + 1];
-  for (uint32_t k = b + 1; k < e; ++k) {
-    const uint32_t v = perm[k];
-    uint32_t q = k;
-    while (q > b && perm[q - 1] > v) {
-      perm[q] = perm[q - 1];
-      --q;
+  uint32_t occ = 0;
+  if (c < ncells) {
+    const uint32_t b = cstart[c], e = cstart[c + 1];
+    for (uint32_t k = b + 1; k < e; ++k) {
+      const uint32_t v = perm[k];
+      uint32_t q = k;
+      while (q > b && perm[q - 1] > v) {
+        perm[q] = perm[q - 1];
+        --q;
+      }
+      perm[q] = v;
     }
-    perm[q] = v;
+    occ = e - b;
   }
-  atomicMax(maxocc, e - b);
+  wave_atomic_max(maxocc, occ);
 }
 
 __global__ void k_gather(const double* __restrict__ x, const uint32_t* __restrict__ perm, uint32_t n, CellGeom g,
@@ -622,23 +625,28 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_particle(SweepArgs A, Cell
   block_commit(A, lb, v, st4);
 }
 
-// U = 1/2 sum u, W = 1/2 sum w (full list counts each pair twice); DO's W is
-// rotated back, W_cart = Q W' Q^T.
+// U = scale sum u, W = scale sum w (scale 1/2 for the full list, which counts
+// each pair twice; 1 for the half list); DO's W is rotated back,
+// W_cart = Q W' Q^T.
 __global__ void k_finalize(const double* __restrict__ partial, uint32_t nb, CellGeom g, double* __restrict__ U,
-                           double* __restrict__ W) {
-  __shared__ double red[4][8];
-  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+                           double* __restrict__ W, double scale, unsigned long long* __restrict__ stats) {
+  __shared__ double red[4][PART_STRIDE];
+  double v[PART_STRIDE] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
-    for (int k = 0; k < 7; ++k) v[k] += partial[8 * (size_t)b + k];
+    for (int k = 0; k < PART_STRIDE; ++k)
+      if (k != 7) v[k] += partial[PART_STRIDE * (size_t)b + k];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < PART_STRIDE; ++k) {
     const double t = warp_sum(v[k]);
     if (lane == 0) red[wid][k] = t;
   }
   __syncthreads();
+  if (threadIdx.x < 4)  // statistics: integers, exact in FP64
+    stats[threadIdx.x] = (unsigned long long)(((red[0][8 + threadIdx.x] + red[1][8 + threadIdx.x]) +
+                                               red[2][8 + threadIdx.x]) + red[3][8 + threadIdx.x]);
   if (threadIdx.x == 0) {
     double s[7];
-    for (int k = 0; k < 7; ++k) s[k] = 0.5 * (((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]);
+    for (int k = 0; k < 7; ++k) s[k] = scale * (((red[0][k] + red[1][k]) + red[2][k]) + red[3][k]);
     U[0] = s[0];
     const double Wp[9] = {s[1], s[4], s[5], s[4], s[2], s[6], s[5], s[6], s[3]};
     if (g.variant == VAR_DO) {
@@ -700,6 +708,18 @@ hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
   const uint32_t n = L.args->n;
   const uint32_t nbrick = (L.mode == SWEEP_TILED) ? (uint32_t)L.args->nbx * L.args->nby * L.args->nbz
                                                   : cdiv(n, SW_THREADS);
+  if (L.mode == SWEEP_HALF) {
+    k_fill_u32<<<1, 64, 0, st>>>((uint32_t*)L.args->stats, 8, 0u);
+    if (n > 0) {
+      const hipError_t e = launch_half(L, st, nbrick);
+      if (e != hipSuccess) return e;
+      k_finalize<<<1, 256, 0, st>>>(L.args->partial, nbrick, *L.g, L.U, L.W, 1.0, L.args->stats);
+    } else {
+      k_zero_f64<<<1, 64, 0, st>>>(L.U, 1);
+      k_zero_f64<<<1, 64, 0, st>>>(L.W, 9);
+    }
+    return hipGetLastError();
+  }
   k_fill_u32<<<1, 64, 0, st>>>((uint32_t*)L.args->stats, 8, 0u);
   k_fill_u32<<<1, 64, 0, st>>>(L.args->overflow, 1, 0u);
   if (n > 0 && nbrick > 0) {
@@ -713,7 +733,7 @@ hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
     NCL_SW(VAR_DS, 0) NCL_SW(VAR_DS, 1) NCL_SW(VAR_DS, 2)
     NCL_SW(VAR_DO, 0) NCL_SW(VAR_DO, 1) NCL_SW(VAR_DO, 2)
 #undef NCL_SW
-    k_finalize<<<1, 256, 0, st>>>(L.args->partial, nbrick, *L.g, L.U, L.W);
+    k_finalize<<<1, 256, 0, st>>>(L.args->partial, nbrick, *L.g, L.U, L.W, 0.5, L.args->stats);
   } else {
     k_zero_f64<<<1, 64, 0, st>>>(L.U, 1);
     k_zero_f64<<<1, 64, 0, st>>>(L.W, 9);

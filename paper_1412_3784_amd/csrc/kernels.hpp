@@ -8,6 +8,11 @@
 
 namespace ncl {
 
+// per-workgroup partial sums of a sweep: [0..6] u, wxx, wyy, wzz, wxy, wxz,
+// wyz; [8..11] statistics (candidates, pairs, FP64 pairs, cells visited),
+// exact as doubles
+constexpr int PART_STRIDE = 12;
+
 struct Pot32 {
   float sig2, eps4, eps24, eps48, shift;
 };
@@ -40,6 +45,8 @@ struct SweepArgs {
   double band64;     // |r^2 - rc^2| below this is re-decided from FP64 positions
   double res_unit;   // value of one unit of the int16 residual
   double rclose2_64; // FP32 modes: pairs closer than this are evaluated in FP64
+  double fix_q, fix_inv;  // half list: fixed-point unit of the LDS force sums and its inverse
+  double rwin2_64;        // half list: pairs closer than this bypass the fixed-point sums
   Pot32 p32;
   Pot64 p64;
 };
@@ -57,18 +64,20 @@ struct BuildLaunch {
   int* err;
 };
 
-enum { SWEEP_TILED = 0, SWEEP_PARTICLE = 1, SWEEP_AUTO = 2 };
+enum { SWEEP_TILED = 0, SWEEP_PARTICLE = 1, SWEEP_AUTO = 2, SWEEP_HALF = 3 };
 
 struct SweepLaunch {
-  int mode;  // SWEEP_TILED or SWEEP_PARTICLE
+  int mode;  // SWEEP_TILED, SWEEP_PARTICLE or SWEEP_HALF
   const CellGeom* g;
   SweepArgs* args;
   int precision;
   bool debug;
   double *U, *W;
+  double* facc;  // SWEEP_HALF: FP64 forces in slot order (3 n)
 };
 
 hipError_t launch_build(const BuildLaunch& L, hipStream_t st);
 hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st);
+hipError_t launch_half(const SweepLaunch& L, hipStream_t st, uint32_t nblocks);
 
 }  // namespace ncl

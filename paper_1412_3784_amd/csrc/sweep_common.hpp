@@ -25,6 +25,14 @@ __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nb) {
 }
 
 
+// atomicMax of v over the wave, one atomic per wave (a counter hit by every
+// thread of a launch serialises in one L2 channel).  Every lane must call it.
+__device__ inline void wave_atomic_max(uint32_t* p, uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_down(v, o, 64));
+  if ((threadIdx.x & 63) == 0 && v != 0) atomicMax(p, v);
+}
+
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
   __shared__ uint32_t wsum[SCAN_THREADS / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -393,10 +401,13 @@ __device__ inline void acc_energy(const Acc<PREC, DEBUG>& acc, double* v) {
   }
 }
 
-// block-wide FP64 sums of v[7] in a fixed order -> partial[8*slot]; integer
-// statistics added atomically.  Every thread of the block must call it.
+// block-wide sums of v[7] (FP64, fixed order) and of the integer statistics
+// -> partial[PART_STRIDE * slot], summed over slots by the finalisation.
+// (Statistics are not added atomically: one counter hit by every wave of a
+// launch serialises in one L2 channel and cost a quarter of the sweep.)
+// Every thread of the block must call it.
 __device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const double* v, const uint32_t* st4) {
-  __shared__ double red[4][8];
+  __shared__ double red[4][PART_STRIDE];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
 #pragma unroll
@@ -404,21 +415,17 @@ __device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const dou
     const double t = warp_sum(v[k]);
     if (lane == 0) red[wid][k] = t;
   }
-  unsigned long long st[4] = {st4[0], st4[1], st4[2], st4[3]};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
+    unsigned long long c = st4[k];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) st[k] += __shfl_down(st[k], o, 64);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (st[k]) atomicAdd(&A.stats[k], st[k]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if (lane == 0) red[wid][8 + k] = (double)c;
   }
   __syncthreads();
-  if (threadIdx.x < 7) {
+  if (threadIdx.x < PART_STRIDE && threadIdx.x != 7) {
     const double t = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-    A.partial[8 * (size_t)slot + threadIdx.x] = t;
+    A.partial[PART_STRIDE * (size_t)slot + threadIdx.x] = t;
   }
 }
 

@@ -22,8 +22,8 @@ NCL_E_ARG, NCL_E_BOX_TOO_SMALL, NCL_E_LATTICE, NCL_E_CAPACITY = -1, -2, -3, -4
 NCL_E_HIP, NCL_E_DEVICE_FLAG, NCL_E_STATE = -5, -6, -7
 NCL_DYNAMIC_SIZE, NCL_DYNAMIC_OFFSET = 0, 1
 NCL_PREC_FP64, NCL_PREC_FP32, NCL_PREC_FP32_KAHAN = 0, 1, 2
-NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS, NCL_OPT_BAND, NCL_OPT_SWEEP = 0, 1, 2, 3
-NCL_SWEEP_TILED, NCL_SWEEP_PARTICLE, NCL_SWEEP_AUTO = 0, 1, 2
+NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS, NCL_OPT_BAND, NCL_OPT_SWEEP, NCL_OPT_DETERMINISTIC = 0, 1, 2, 3, 4
+NCL_SWEEP_TILED, NCL_SWEEP_PARTICLE, NCL_SWEEP_AUTO, NCL_SWEEP_HALF = 0, 1, 2, 3
 
 VARIANTS = {"ds": NCL_DYNAMIC_SIZE, "do": NCL_DYNAMIC_OFFSET}
 PRECISIONS = {"fp64": NCL_PREC_FP64, "fp32": NCL_PREC_FP32, "fp32k": NCL_PREC_FP32_KAHAN}
@@ -48,7 +48,7 @@ class ncl_stats(ctypes.Structure):
                 ("cells", ctypes.c_int32 * 3), ("max_occupancy", ctypes.c_int32), ("ncells", ctypes.c_int64),
                 ("candidates", ctypes.c_int64), ("pairs", ctypes.c_int64), ("fp64_pairs", ctypes.c_int64),
                 ("neighbourhood", ctypes.c_int64), ("sweep", ctypes.c_int32), ("brick", ctypes.c_int32 * 3),
-                ("tune_ms", ctypes.c_float * 4)]
+                ("tune_ms", ctypes.c_float * 5)]
 
 
 def _load():

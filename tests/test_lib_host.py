@@ -92,6 +92,16 @@ def test_error_codes(ncl):
         with pytest.raises(ncl.NclError) as e:
             ncl.ncl_set_option(h, 99, 1.0)
         assert e.value.code == ncl.NCL_E_ARG
+        # sweep schedules 0..3 (3: half list) and the determinism switch
+        for v in (0, 1, 2, 3):
+            ncl.ncl_set_option(h, ncl.NCL_OPT_SWEEP, v)
+        for opt, v in ((ncl.NCL_OPT_SWEEP, 4), (ncl.NCL_OPT_DETERMINISTIC, 2)):
+            with pytest.raises(ncl.NclError) as e:
+                ncl.ncl_set_option(h, opt, v)
+            assert e.value.code == ncl.NCL_E_ARG
+        ncl.ncl_set_option(h, ncl.NCL_OPT_DETERMINISTIC, 0)
+        ncl.ncl_set_option(h, ncl.NCL_OPT_DETERMINISTIC, 1)
+        ncl.ncl_set_option(h, ncl.NCL_OPT_SWEEP, ncl.NCL_SWEEP_AUTO)
         # forces before any build
         with pytest.raises(ncl.NclError) as e:
             ncl._check(h, ncl._lib.ncl_compute_forces(h, None, None, None))
