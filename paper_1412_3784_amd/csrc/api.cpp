@@ -44,8 +44,9 @@ struct ncl_ctx {
   CellGeom geom;
   // scratch
   size_t cap_n = 0, cap_cells = 0, cap_scan = 0, cap_blocks = 0, cap_wrap = 0, cap_dbgF = 0;
-  uint32_t *cell_of = nullptr, *rank = nullptr, *count = nullptr, *cstart = nullptr, *perm = nullptr,
-           *scan_tmp = nullptr;
+  uint32_t *cell_of = nullptr, *rank = nullptr, *cstart = nullptr, *perm = nullptr, *scan_tmp = nullptr,
+           *rs_val = nullptr, *rs_hist = nullptr, *rs_off = nullptr;
+  size_t cap_rs = 0;
   double4* pos64 = nullptr;
   float4* pos32 = nullptr;
   float4* pos32lo = nullptr;
@@ -132,8 +133,9 @@ int ncl_destroy(ncl_handle h) {
   int code = NCL_OK;
   if (h->small) {  // device state exists only after a build
     if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) code = NCL_E_HIP;
-    void* bufs[] = {h->cell_of, h->rank,    h->count, h->cstart,  h->perm,     h->scan_tmp, h->pos64, h->pos32,
-                    h->pos32lo, h->wrap,    h->partial, h->overflow, h->dbgF, h->facc,     h->small};
+    void* bufs[] = {h->cell_of, h->rank,   h->cstart,  h->perm,     h->scan_tmp, h->pos64,
+                    h->pos32,   h->pos32lo, h->wrap,  h->partial,  h->overflow, h->dbgF,
+                    h->facc,    h->rs_val,  h->rs_hist, h->rs_off, h->small};
     for (void* b : bufs)
       if (b && hipFree(b) != hipSuccess) code = NCL_E_HIP;
   }
@@ -349,8 +351,8 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   const size_t un = (size_t)n;
   if (un > h->cap_n || !h->perm) {
     // per-particle arrays, all sized for cap_n particles
-    void** bufs[] = {(void**)&h->cell_of, (void**)&h->rank, (void**)&h->perm, (void**)&h->pos64,
-                     (void**)&h->pos32, (void**)&h->pos32lo};
+    void** bufs[] = {(void**)&h->cell_of, (void**)&h->rank,    (void**)&h->perm,  (void**)&h->pos64,
+                     (void**)&h->pos32,   (void**)&h->pos32lo, (void**)&h->rs_val};
     for (void** b : bufs)
       if (*b) {
         HIPCHK(h, hipFree(*b));
@@ -364,17 +366,29 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
     HIPCHK(h, hipMalloc((void**)&h->pos64, m * sizeof(double4)));
     HIPCHK(h, hipMalloc((void**)&h->pos32, m * sizeof(float4)));
     HIPCHK(h, hipMalloc((void**)&h->pos32lo, m * sizeof(float4)));
+    HIPCHK(h, hipMalloc((void**)&h->rs_val, m * sizeof(uint32_t)));
     h->cap_n = m;
   }
   if (debug) HIPCHK(h, grow(&h->wrap, &h->cap_wrap, un));
   if (want_cells > h->cap_cells || !h->cstart) {
-    if (h->count) HIPCHK(h, hipFree(h->count));
     if (h->cstart) HIPCHK(h, hipFree(h->cstart));
-    h->count = h->cstart = nullptr;
+    h->cstart = nullptr;
     h->cap_cells = 0;
-    HIPCHK(h, hipMalloc((void**)&h->count, want_cells * sizeof(uint32_t)));
     HIPCHK(h, hipMalloc((void**)&h->cstart, want_cells * sizeof(uint32_t)));
     h->cap_cells = want_cells;
+  }
+  // radix sort of the cell keys: (digit, tile) counts and offsets
+  {
+    const size_t nrs = rs_offsets((uint32_t)un);
+    if (nrs > h->cap_rs || !h->rs_hist) {
+      if (h->rs_hist) HIPCHK(h, hipFree(h->rs_hist));
+      if (h->rs_off) HIPCHK(h, hipFree(h->rs_off));
+      h->rs_hist = h->rs_off = nullptr;
+      h->cap_rs = 0;
+      HIPCHK(h, hipMalloc((void**)&h->rs_hist, nrs * sizeof(uint32_t)));
+      HIPCHK(h, hipMalloc((void**)&h->rs_off, nrs * sizeof(uint32_t)));
+      h->cap_rs = nrs;
+    }
   }
   choose_brick(h, g, (size_t)n, nc);
   {
@@ -388,11 +402,12 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
       h->partial = nullptr;
       h->cap_bricks = 0;
       HIPCHK(h, hipMalloc((void**)&h->overflow, (nbr + 2) * sizeof(uint32_t)));
-      HIPCHK(h, hipMalloc((void**)&h->partial, PART_STRIDE * (nbr + 2) * sizeof(double)));
+      // block partials, then their second-level sums (one per 256 blocks)
+      HIPCHK(h, hipMalloc((void**)&h->partial, PART_STRIDE * (nbr + 2 + (nbr + 2) / 256 + 1) * sizeof(double)));
       h->cap_bricks = nbr + 2;
     }
   }
-  const size_t nscan = ((size_t)nc + 2047) / 2048 + 1;
+  const size_t nscan = rs_offsets((uint32_t)un) / 2048 + 2;
   HIPCHK(h, grow(&h->scan_tmp, &h->cap_scan, nscan));
   if (precision == NCL_PREC_FP32 &&
       (h->sweep_mode == SWEEP_HALF || (h->sweep_mode == SWEEP_AUTO && !h->deterministic)))
@@ -412,11 +427,12 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   L.ncells = nc;
   L.cell_of = h->cell_of;
   L.rank = h->rank;
-  L.count = h->count;
+  L.rs_val = h->rs_val;
+  L.rs_hist = h->rs_hist;
+  L.rs_off = h->rs_off;
   L.cstart = h->cstart;
   L.perm = h->perm;
   L.scan_tmp = h->scan_tmp;
-  L.maxocc = (uint32_t*)(h->small + 4);
   L.pos64 = h->pos64;
   L.pos32 = h->pos32;
   L.pos32lo = h->pos32lo;
@@ -476,6 +492,7 @@ static void fill_sweep_args(ncl_ctx* h, SweepArgs* A, void* F) {
   A->wrap = h->wrap;
   A->F = F;
   A->partial = h->partial;
+  A->partial2 = h->partial + PART_STRIDE * h->cap_bricks;
   A->stats = h->small;
   A->dbg_count = nullptr;
   A->dbg_hash = nullptr;
@@ -656,6 +673,10 @@ int ncl_get_stats(ncl_handle h, ncl_stats* out) {
   if (!h || !out) return NCL_E_ARG;
   if (!h->small) return fail(h, NCL_E_STATE, "nothing built yet");
   HIPCHK(h, hipSetDevice(h->device));
+  if (h->built && h->cstart) {
+    const hipError_t e = launch_max_occupancy(h->cstart, h->ncells, (uint32_t*)(h->small + 4), h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "occupancy");
+  }
   unsigned long long w[8];
   HIPCHK(h, hipMemcpyAsync(w, h->small, sizeof w, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));

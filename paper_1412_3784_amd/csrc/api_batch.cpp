@@ -87,7 +87,6 @@ static BatchDev view(ncl_batch* b) {
   D.lred = b->lred;
   D.step = b->small + 10;
   D.err = (int*)(b->small + 9);
-  D.maxocc = b->small + 8;
   D.cell_of = b->cell_of;
   D.rank = b->rank;
   D.rep = b->rep;
@@ -119,6 +118,7 @@ static void sweep_args(ncl_batch* b, SweepArgs* A, void* F) {
   A->wrap = b->wrap;
   A->F = F;
   A->partial = b->partial;
+  A->partial2 = nullptr;  // per-replica finalisation reads the block partials directly
   A->stats = (unsigned long long*)b->small;
   A->n = (uint32_t)b->nslots;
   A->rc2 = rc2;
@@ -342,6 +342,7 @@ int ncl_batch_debug_pairs(ncl_batch_handle b, int64_t* count, uint64_t* hash) {
 int ncl_batch_get_stats(ncl_batch_handle b, ncl_stats* out) {
   if (!b || !out) return NCL_E_ARG;
   BCHK(b, hipSetDevice(b->device));
+  if (b->built && b->cstart) BCHK(b, launch_max_occupancy(b->cstart, b->ncells, b->small + 8, b->stream));
   uint32_t w[16];
   BCHK(b, hipMemcpyAsync(w, b->small, sizeof w, hipMemcpyDeviceToHost, b->stream));
   BCHK(b, hipStreamSynchronize(b->stream));

@@ -96,25 +96,21 @@ __global__ void kb_scatter(BatchDev D) {
 
 __global__ void kb_cell_sort(BatchDev D) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t occ = 0;
-  // (non-finite input: cells may be huge, the sort is skipped)
-  if (c < D.ncells && !(D.err[0] & 1)) {
-    const uint32_t r = find_rep(D.cell_off, D.nrep, c);
-    const uint32_t pad = D.slot_off[r] - D.n_off[r];
-    const uint32_t b = D.cstart[c] + pad, e = D.cstart[c + 1] + pad;
-    uint32_t* perm = D.perm;
-    for (uint32_t k = b + 1; k < e; ++k) {
-      const uint32_t v = perm[k];
-      uint32_t q = k;
-      while (q > b && perm[q - 1] > v) {
-        perm[q] = perm[q - 1];
-        --q;
-      }
-      perm[q] = v;
+  if (c >= D.ncells) return;
+  if (D.err[0] & 1) return;  // non-finite input: cells may be huge, skip the sort
+  const uint32_t r = find_rep(D.cell_off, D.nrep, c);
+  const uint32_t pad = D.slot_off[r] - D.n_off[r];
+  const uint32_t b = D.cstart[c] + pad, e = D.cstart[c + 1] + pad;
+  uint32_t* perm = D.perm;
+  for (uint32_t k = b + 1; k < e; ++k) {
+    const uint32_t v = perm[k];
+    uint32_t q = k;
+    while (q > b && perm[q - 1] > v) {
+      perm[q] = perm[q - 1];
+      --q;
     }
-    occ = e - b;
+    perm[q] = v;
   }
-  wave_atomic_max(D.maxocc, occ);
 }
 
 __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
@@ -340,7 +336,6 @@ hipError_t batch_prologue(const BatchDev& D, int off, double h, hipStream_t st) 
 hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
   kb_fill_u32<<<cdivb(D.ncells, 256), 256, 0, st>>>(D.count, D.ncells, 0u);
   kb_fill_u32<<<cdivb(D.nslots, 256), 256, 0, st>>>(D.perm, D.nslots, PAD_SLOT);
-  kb_fill_u32<<<1, 64, 0, st>>>(D.maxocc, 1, 0u);
   if (D.n > 0) kb_bin_count<<<cdivb(D.n, 256), 256, 0, st>>>(D, x);
   hipError_t e = scan_counts(D.count, D.ncells, D.scan_tmp, D.cstart, st);
   if (e != hipSuccess) return e;

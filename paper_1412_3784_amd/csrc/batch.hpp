@@ -24,7 +24,6 @@ struct BatchDev {
   double* lred;              // [nrep*9] current reduced basis
   uint32_t* step;            // device step counter
   int* err;
-  uint32_t* maxocc;
   uint32_t *cell_of, *rank, *rep, *count, *cstart, *scan_tmp, *perm;
   double4* pos64;
   float4* pos32;

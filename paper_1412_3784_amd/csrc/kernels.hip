@@ -37,129 +37,6 @@ __global__ void k_zero_f64(double* __restrict__ p, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// binning
-// ---------------------------------------------------------------------------
-__global__ void k_bin_count(const double* __restrict__ x, uint32_t n, CellGeom g, uint32_t* __restrict__ cell_of,
-                            uint32_t* __restrict__ rank, uint32_t* __restrict__ count, int* __restrict__ err) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
-  double xw[3];
-  int32_t img[3];
-  bool bad = false;
-  const uint32_t c = locate(g, p, xw, img, &bad);
-  if (bad) atomicOr(err, 1);
-  cell_of[i] = c;
-  rank[i] = atomicAdd(&count[c], 1u);
-}
-
-// exclusive scan of u32 counts, three passes: per-block totals, a scan of
-// the totals in one block, then the per-block scan with its offset.
-constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
-
-__global__ void k_scan_totals(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tot) {
-  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) s += (base + k < n) ? in[base + k] : 0u;
-  uint32_t total;
-  block_excl_scan(s, &total);
-  if (threadIdx.x == 0) tot[blockIdx.x] = total;
-}
-
-__global__ void k_scan_top(uint32_t* __restrict__ tot, uint32_t nb) {
-  // one block: exclusive scan of the block totals in place, in chunks
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < nb; base += SCAN_THREADS) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < nb ? tot[i] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(v, &total);
-    if (i < nb) tot[i] = carry + ex;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += total;
-    __syncthreads();
-  }
-}
-
-__global__ void k_scan_apply(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ tot,
-                             uint32_t* __restrict__ out) {
-  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-  uint32_t v[SCAN_ITEMS], s = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    v[k] = (base + k < n) ? in[base + k] : 0u;
-    s += v[k];
-  }
-  uint32_t total;
-  uint32_t run = tot[blockIdx.x] + block_excl_scan(s, &total);
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
-  }
-  if (base < n && base + SCAN_ITEMS >= n) out[n] = run;  // the thread holding the last element
-}
-
-__global__ void k_scatter(const uint32_t* __restrict__ cell_of, const uint32_t* __restrict__ rank, uint32_t n,
-                          const uint32_t* __restrict__ cstart, uint32_t* __restrict__ perm) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  perm[cstart[cell_of[i]] + rank[i]] = i;
-}
-
-// order each cell's particles by input index (insertion sort; cells hold a
-// handful of particles), and record the largest occupancy
-__global__ void k_cell_sort(const uint32_t* __restrict__ cstart, uint32_t ncells, uint32_t* __restrict__ perm,
-                            uint32_t* __restrict__ maxocc) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t occ = 0;
-  if (c < ncells) {
-    const uint32_t b = cstart[c], e = cstart[c + 1];
-    for (uint32_t k = b + 1; k < e; ++k) {
-      const uint32_t v = perm[k];
-      uint32_t q = k;
-      while (q > b && perm[q - 1] > v) {
-        perm[q] = perm[q - 1];
-        --q;
-      }
-      perm[q] = v;
-    }
-    occ = e - b;
-  }
-  wave_atomic_max(maxocc, occ);
-}
-
-__global__ void k_gather(const double* __restrict__ x, const uint32_t* __restrict__ perm, uint32_t n, CellGeom g,
-                         double4* __restrict__ pos64, float4* __restrict__ pos32, float4* __restrict__ pos32lo,
-                         int4* __restrict__ wrap) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const uint32_t i = perm[s];
-  const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
-  double xw[3];
-  int32_t img[3];
-  bool bad = false;
-  const uint32_t c = locate(g, p, xw, img, &bad);
-  const int a = (int)(c % (uint32_t)g.nc[0]);
-  const int b = (int)((c / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
-  const int cz = (int)(c / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
-  double cen[3];
-  cell_centre(g, a, b, cz, cen);
-  pos64[s] = make_double4(xw[0], xw[1], xw[2], 0.0);
-  // FP32 offset from the cell centre as a hi + lo pair (hi + lo carries the
-  // FP64 offset to ~48 bits); the sweep screens with hi alone
-  const double o[3] = {xw[0] - cen[0], xw[1] - cen[1], xw[2] - cen[2]};
-  const float hi[3] = {(float)o[0], (float)o[1], (float)o[2]};
-  pos32[s] = make_float4(hi[0], hi[1], hi[2], __uint_as_float(c));
-  pos32lo[s] = make_float4((float)(o[0] - hi[0]), (float)(o[1] - hi[1]), (float)(o[2] - hi[2]), 0.f);
-  if (wrap) wrap[s] = make_int4(img[0], img[1], img[2], 0);
-}
-
-// ---------------------------------------------------------------------------
 // the neighbourhood sweep
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
@@ -625,6 +502,23 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_particle(SweepArgs A, Cell
   block_commit(A, lb, v, st4);
 }
 
+// first level of the fixed-order reduction: block r sums partial slots
+// [256 r, 256 r + 256) into out[r]
+__global__ void __launch_bounds__(256) k_reduce_partials(const double* __restrict__ partial, uint32_t nb,
+                                                         double* __restrict__ out) {
+  __shared__ double red[4][PART_STRIDE];
+  const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < PART_STRIDE; ++k) {
+    const double t = warp_sum((b < nb && k != 7) ? partial[PART_STRIDE * (size_t)b + k] : 0.0);
+    if (lane == 0) red[wid][k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < PART_STRIDE)
+    out[PART_STRIDE * (size_t)blockIdx.x + threadIdx.x] =
+        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
 // U = scale sum u, W = scale sum w (scale 1/2 for the full list, which counts
 // each pair twice; 1 for the half list); DO's W is rotated back,
 // W_cart = Q W' Q^T.
@@ -669,29 +563,12 @@ __global__ void k_finalize(const double* __restrict__ partial, uint32_t nb, Cell
 // ---------------------------------------------------------------------------
 static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
-// exclusive scan of n counts into out[0..n] (out[n] = total); tmp holds
-// ceil(n / SCAN_TILE) block totals
-hipError_t scan_counts(const uint32_t* count, uint32_t n, uint32_t* tmp, uint32_t* out, hipStream_t st) {
-  const uint32_t nb = cdiv(n, SCAN_TILE);
-  if (nb == 0) return hipSuccess;
-  k_scan_totals<<<nb, SCAN_THREADS, 0, st>>>(count, n, tmp);
-  k_scan_top<<<1, SCAN_THREADS, 0, st>>>(tmp, nb);
-  k_scan_apply<<<nb, SCAN_THREADS, 0, st>>>(count, n, tmp, out);
-  return hipGetLastError();
-}
 
-hipError_t launch_build(const BuildLaunch& L, hipStream_t st) {
-  const uint32_t n = L.n, nc = L.ncells;
-  if (nc > 0) k_fill_u32<<<cdiv(nc, 256), 256, 0, st>>>(L.count, nc, 0u);
-  k_fill_u32<<<1, 64, 0, st>>>(L.maxocc, 1, 0u);
-  if (n > 0) k_bin_count<<<cdiv(n, 256), 256, 0, st>>>(L.x, n, *L.g, L.cell_of, L.rank, L.count, L.err);
-  scan_counts(L.count, nc, L.scan_tmp, L.cstart, st);
-  if (n > 0) {
-    k_scatter<<<cdiv(n, 256), 256, 0, st>>>(L.cell_of, L.rank, n, L.cstart, L.perm);
-    k_cell_sort<<<cdiv(nc, 256), 256, 0, st>>>(L.cstart, nc, L.perm, L.maxocc);
-    k_gather<<<cdiv(n, 256), 256, 0, st>>>(L.x, L.perm, n, *L.g, L.pos64, L.pos32, L.pos32lo, L.wrap);
-  }
-  return hipGetLastError();
+// two-level fixed-order reduction of the nb partial slots into U, W, stats
+static void finalize(const SweepLaunch& L, hipStream_t st, uint32_t nb, double scale) {
+  const uint32_t nr = cdiv(nb, 256);
+  k_reduce_partials<<<nr, 256, 0, st>>>(L.args->partial, nb, L.args->partial2);
+  k_finalize<<<1, 256, 0, st>>>(L.args->partial2, nr, *L.g, L.U, L.W, scale, L.args->stats);
 }
 
 template <int VAR, int PREC, bool DEBUG>
@@ -713,7 +590,7 @@ hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
     if (n > 0) {
       const hipError_t e = launch_half(L, st, nbrick);
       if (e != hipSuccess) return e;
-      k_finalize<<<1, 256, 0, st>>>(L.args->partial, nbrick, *L.g, L.U, L.W, 1.0, L.args->stats);
+      finalize(L, st, nbrick, 1.0);
     } else {
       k_zero_f64<<<1, 64, 0, st>>>(L.U, 1);
       k_zero_f64<<<1, 64, 0, st>>>(L.W, 9);
@@ -733,7 +610,7 @@ hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
     NCL_SW(VAR_DS, 0) NCL_SW(VAR_DS, 1) NCL_SW(VAR_DS, 2)
     NCL_SW(VAR_DO, 0) NCL_SW(VAR_DO, 1) NCL_SW(VAR_DO, 2)
 #undef NCL_SW
-    k_finalize<<<1, 256, 0, st>>>(L.args->partial, nbrick, *L.g, L.U, L.W, 0.5, L.args->stats);
+    finalize(L, st, nbrick, 0.5);
   } else {
     k_zero_f64<<<1, 64, 0, st>>>(L.U, 1);
     k_zero_f64<<<1, 64, 0, st>>>(L.W, 9);

@@ -29,6 +29,7 @@ struct SweepArgs {
   const int4* wrap;
   void* F;
   double* partial;
+  double* partial2;        // second-level sums of partial, one per 256 slots
   unsigned long long* stats;
   int64_t* dbg_count;
   uint64_t* dbg_hash;
@@ -56,7 +57,9 @@ struct BuildLaunch {
   const CellGeom* g;
   const double* x;
   uint32_t n, ncells;
-  uint32_t *cell_of, *rank, *count, *cstart, *perm, *scan_tmp, *maxocc;
+  // cell_of, rank: radix-sort keys (ping-pong); rs_val: values; rs_hist,
+  // rs_off: rs_offsets(n) words each; scan_tmp: scan block totals of rs_hist
+  uint32_t *cell_of, *rank, *rs_val, *rs_hist, *rs_off, *cstart, *perm, *scan_tmp;
   double4* pos64;
   float4* pos32;
   float4* pos32lo;
@@ -77,6 +80,10 @@ struct SweepLaunch {
 };
 
 hipError_t launch_build(const BuildLaunch& L, hipStream_t st);
+uint32_t rs_tiles(uint32_t n);
+// largest of cstart[c + 1] - cstart[c] over c < nc into *out (statistics)
+hipError_t launch_max_occupancy(const uint32_t* cstart, uint32_t nc, uint32_t* out, hipStream_t st);
+size_t rs_offsets(uint32_t n);
 hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st);
 hipError_t launch_half(const SweepLaunch& L, hipStream_t st, uint32_t nblocks);
 

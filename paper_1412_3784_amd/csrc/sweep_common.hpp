@@ -25,14 +25,6 @@ __device__ inline uint32_t xcd_block(uint32_t bid, uint32_t nb) {
 }
 
 
-// atomicMax of v over the wave, one atomic per wave (a counter hit by every
-// thread of a launch serialises in one L2 channel).  Every lane must call it.
-__device__ inline void wave_atomic_max(uint32_t* p, uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_down(v, o, 64));
-  if ((threadIdx.x & 63) == 0 && v != 0) atomicMax(p, v);
-}
-
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
   __shared__ uint32_t wsum[SCAN_THREADS / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
