@@ -38,7 +38,8 @@ struct ncl_batch {
   double *t0_d = nullptr, *adiag = nullptr, *lred = nullptr, *kpart = nullptr, *partial = nullptr;
   CellGeom* geom = nullptr;
   uint32_t* small = nullptr;  // [0..7] stats (4 u64), [8] maxocc, [9] err, [10] step
-  uint32_t *cell_of = nullptr, *rank = nullptr, *rep = nullptr, *count = nullptr, *cstart = nullptr,
+  uint32_t *rs_va = nullptr, *rs_vb = nullptr, *rs_hist = nullptr, *rs_off = nullptr;
+  uint32_t *cell_of = nullptr, *rank = nullptr, *rep = nullptr, *cstart = nullptr,
            *scan_tmp = nullptr, *perm = nullptr;
   double4* pos64 = nullptr;
   float4* pos32 = nullptr;
@@ -90,7 +91,10 @@ static BatchDev view(ncl_batch* b) {
   D.cell_of = b->cell_of;
   D.rank = b->rank;
   D.rep = b->rep;
-  D.count = b->count;
+  D.rs_va = b->rs_va;
+  D.rs_vb = b->rs_vb;
+  D.rs_hist = b->rs_hist;
+  D.rs_off = b->rs_off;
   D.cstart = b->cstart;
   D.scan_tmp = b->scan_tmp;
   D.perm = b->perm;
@@ -140,8 +144,8 @@ static void sweep_args(ncl_batch* b, SweepArgs* A, void* F) {
 static void free_all(ncl_batch* b) {
   void* bufs[] = {b->n_off,  b->slot_off, b->cell_off, b->blk_rep, b->pol,     b->t0_d,    b->adiag,
                   b->lred,   b->kpart,    b->partial,  b->geom,    b->small,   b->cell_of, b->rank,
-                  b->rep,    b->count,    b->cstart,   b->scan_tmp, b->perm,   b->pos64,   b->pos32,
-                  b->pos32lo, b->wrap,    b->dbgF};
+                  b->rep,    b->cstart,   b->scan_tmp, b->perm,   b->pos64,   b->pos32,   b->pos32lo,
+                  b->wrap,   b->dbgF,     b->rs_va,    b->rs_vb,   b->rs_hist, b->rs_off};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -185,6 +189,11 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->cell_of, tot);
   if (e == hipSuccess) e = dalloc(&b->rank, tot);
   if (e == hipSuccess) e = dalloc(&b->rep, tot);
+  if (e == hipSuccess) e = dalloc(&b->rs_va, tot);
+  if (e == hipSuccess) e = dalloc(&b->rs_vb, tot);
+  if (e == hipSuccess) e = dalloc(&b->rs_hist, rs_offsets((uint32_t)tot));
+  if (e == hipSuccess) e = dalloc(&b->rs_off, rs_offsets((uint32_t)tot));
+  if (e == hipSuccess) e = dalloc(&b->scan_tmp, rs_offsets((uint32_t)tot) / 2048 + 2);
   if (e == hipSuccess) e = dalloc(&b->partial, PART_STRIDE * (slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->kpart, 3 * (slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->pol, nrep);
@@ -277,15 +286,11 @@ int ncl_batch_set_lattices(ncl_batch_handle b, int variant, const double* L0, co
     coff[r + 1] = coff[r] + (uint32_t)cap;
   }
   const uint64_t ncells = coff[R];
-  if (ncells != b->ncells || !b->count) {
-    if (b->count) (void)hipFree(b->count);
+  if (ncells != b->ncells || !b->cstart) {
     if (b->cstart) (void)hipFree(b->cstart);
-    if (b->scan_tmp) (void)hipFree(b->scan_tmp);
     if (b->cell_off) (void)hipFree(b->cell_off);
-    b->count = b->cstart = b->scan_tmp = b->cell_off = nullptr;
-    BCHK(b, dalloc(&b->count, ncells));
+    b->cstart = b->cell_off = nullptr;
     BCHK(b, dalloc(&b->cstart, ncells + 1));
-    BCHK(b, dalloc(&b->scan_tmp, ncells / 2048 + 2));
     BCHK(b, dalloc(&b->cell_off, (size_t)R + 1));
     b->ncells = ncells;
   }

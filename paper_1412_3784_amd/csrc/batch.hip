@@ -72,7 +72,7 @@ __global__ void kb_prologue(BatchDev D, int off, double h) {
   D.geom[r] = g;
 }
 
-__global__ void kb_bin_count(BatchDev D, const double* __restrict__ x) {
+__global__ void kb_cell_index(BatchDev D, const double* __restrict__ x) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D.n) return;
   const uint32_t r = find_rep(D.n_off, D.nrep, i);
@@ -84,33 +84,15 @@ __global__ void kb_bin_count(BatchDev D, const double* __restrict__ x) {
   if (bad) atomicOr(D.err, 1);
   D.cell_of[i] = c;
   D.rep[i] = r;
-  D.rank[i] = atomicAdd(&D.count[c], 1u);
 }
 
-__global__ void kb_scatter(BatchDev D) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.n) return;
-  const uint32_t r = D.rep[i];
-  D.perm[D.cstart[D.cell_of[i]] + D.rank[i] + (D.slot_off[r] - D.n_off[r])] = i;
-}
-
-__global__ void kb_cell_sort(BatchDev D) {
-  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.ncells) return;
-  if (D.err[0] & 1) return;  // non-finite input: cells may be huge, skip the sort
-  const uint32_t r = find_rep(D.cell_off, D.nrep, c);
-  const uint32_t pad = D.slot_off[r] - D.n_off[r];
-  const uint32_t b = D.cstart[c] + pad, e = D.cstart[c + 1] + pad;
-  uint32_t* perm = D.perm;
-  for (uint32_t k = b + 1; k < e; ++k) {
-    const uint32_t v = perm[k];
-    uint32_t q = k;
-    while (q > b && perm[q - 1] > v) {
-      perm[q] = perm[q - 1];
-      --q;
-    }
-    perm[q] = v;
-  }
+// sorted position s (replica-major, cells in order) -> slot in the
+// replica's padded range
+__global__ void kb_place(BatchDev D, const uint32_t* __restrict__ keys) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= D.n) return;
+  const uint32_t r = find_rep(D.cell_off, D.nrep, keys[s]);
+  D.perm[s + (D.slot_off[r] - D.n_off[r])] = D.rs_va[s];
 }
 
 __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
@@ -334,14 +316,15 @@ hipError_t batch_prologue(const BatchDev& D, int off, double h, hipStream_t st) 
 }
 
 hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
-  kb_fill_u32<<<cdivb(D.ncells, 256), 256, 0, st>>>(D.count, D.ncells, 0u);
   kb_fill_u32<<<cdivb(D.nslots, 256), 256, 0, st>>>(D.perm, D.nslots, PAD_SLOT);
-  if (D.n > 0) kb_bin_count<<<cdivb(D.n, 256), 256, 0, st>>>(D, x);
-  hipError_t e = scan_counts(D.count, D.ncells, D.scan_tmp, D.cstart, st);
+  if (D.n > 0) kb_cell_index<<<cdivb(D.n, 256), 256, 0, st>>>(D, x);
+  const uint32_t* keys = D.cell_of;
+  hipError_t e = radix_sort_cells(D.cell_of, D.rank, D.rs_va, D.rs_vb, D.n, D.ncells, D.rs_hist, D.rs_off,
+                                  D.scan_tmp, &keys, st);
+  if (e == hipSuccess) e = cell_starts(keys, D.n, D.ncells, D.cstart, st);
   if (e != hipSuccess) return e;
   if (D.n > 0) {
-    kb_scatter<<<cdivb(D.n, 256), 256, 0, st>>>(D);
-    kb_cell_sort<<<cdivb(D.ncells, 256), 256, 0, st>>>(D);
+    kb_place<<<cdivb(D.n, 256), 256, 0, st>>>(D, keys);
     kb_gather<<<cdivb(D.nslots, 256), 256, 0, st>>>(D, x);
   }
   return hipGetLastError();

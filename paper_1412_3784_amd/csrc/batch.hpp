@@ -24,7 +24,8 @@ struct BatchDev {
   double* lred;              // [nrep*9] current reduced basis
   uint32_t* step;            // device step counter
   int* err;
-  uint32_t *cell_of, *rank, *rep, *count, *cstart, *scan_tmp, *perm;
+  uint32_t *cell_of, *rank, *rep, *cstart, *scan_tmp, *perm;
+  uint32_t *rs_va, *rs_vb, *rs_hist, *rs_off;  // radix sort of the cell keys
   double4* pos64;
   float4* pos32;
   float4* pos32lo;
@@ -32,7 +33,6 @@ struct BatchDev {
   double* kpart;             // [nslots/256*3] kinetic partial sums
 };
 
-hipError_t scan_counts(const uint32_t* count, uint32_t n, uint32_t* tmp, uint32_t* out, hipStream_t st);
 hipError_t batch_prologue(const BatchDev& D, int off, double h, hipStream_t st);
 hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st);
 hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, bool debug, double* U, double* W,

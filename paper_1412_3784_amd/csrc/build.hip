@@ -243,7 +243,7 @@ static inline uint32_t bdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b -
 
 // exclusive scan of n counts into out[0..n] (out[n] = total); tmp holds
 // ceil(n / SCAN_TILE) block totals
-hipError_t scan_counts(const uint32_t* count, uint32_t n, uint32_t* tmp, uint32_t* out, hipStream_t st) {
+static hipError_t scan_counts(const uint32_t* count, uint32_t n, uint32_t* tmp, uint32_t* out, hipStream_t st) {
   const uint32_t nb = bdiv(n, SCAN_TILE);
   if (nb == 0) return hipSuccess;
   k_scan_totals<<<nb, SCAN_THREADS, 0, st>>>(count, n, tmp);
@@ -261,31 +261,42 @@ hipError_t launch_max_occupancy(const uint32_t* cstart, uint32_t nc, uint32_t* o
 uint32_t rs_tiles(uint32_t n) { return bdiv(n, RS_TILE); }
 size_t rs_offsets(uint32_t n) { return (size_t)256 * rs_tiles(n) + 1; }
 
-hipError_t launch_build(const BuildLaunch& L, hipStream_t st) {
-  const uint32_t n = L.n, nc = L.ncells;
-  if (n == 0) {
-    k_bfill_u32<<<bdiv(nc + 1, 256), 256, 0, st>>>(L.cstart, nc + 1, 0u);
-    return hipGetLastError();
-  }
-  k_cell_index<<<bdiv(n, 256), 256, 0, st>>>(L.x, n, *L.g, L.cell_of, L.err);
-  // 8-bit digits over the bits of the largest cell index
+hipError_t radix_sort_cells(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, uint32_t n,
+                            uint32_t nkeys, uint32_t* hist, uint32_t* off, uint32_t* scan_tmp,
+                            const uint32_t** sorted_keys, hipStream_t st) {
+  // 8-bit digits over the bits of the largest key
   int bits = 1;
-  while (bits < 32 && ((nc - 1u) >> bits) != 0u) ++bits;
+  while (bits < 32 && ((nkeys - 1u) >> bits) != 0u) ++bits;
   const int passes = (bits + 7) / 8;
   const uint32_t nt = rs_tiles(n), nh = 256u * nt;
-  // keys ping-pong between cell_of and rank; values end in perm
-  uint32_t* kb[2] = {L.cell_of, L.rank};
-  uint32_t* vb[2] = {(passes & 1) ? L.perm : L.rs_val, (passes & 1) ? L.rs_val : L.perm};
-  for (int p = 0; p < passes; ++p) {
-    k_rs_hist<<<nt, RS_THREADS, 0, st>>>(kb[p & 1], n, 8 * p, L.rs_hist, nt);
-    hipError_t e = scan_counts(L.rs_hist, nh, L.scan_tmp, L.rs_off, st);
+  // keys ping-pong between keys and keys_alt; values end in vals
+  uint32_t* kb[2] = {keys, keys_alt};
+  uint32_t* vb[2] = {(passes & 1) ? vals : vals_alt, (passes & 1) ? vals_alt : vals};
+  for (int p = 0; p < passes && n > 0; ++p) {
+    k_rs_hist<<<nt, RS_THREADS, 0, st>>>(kb[p & 1], n, 8 * p, hist, nt);
+    const hipError_t e = scan_counts(hist, nh, scan_tmp, off, st);
     if (e != hipSuccess) return e;
-    k_rs_scatter<<<nt, RS_THREADS, 0, st>>>(kb[p & 1], p ? vb[(p - 1) & 1] : nullptr, n, 8 * p, L.rs_hist,
-                                            L.rs_off, nt, kb[(p + 1) & 1], vb[p & 1]);
+    k_rs_scatter<<<nt, RS_THREADS, 0, st>>>(kb[p & 1], p ? vb[(p - 1) & 1] : nullptr, n, 8 * p, hist, off, nt,
+                                            kb[(p + 1) & 1], vb[p & 1]);
   }
-  const uint32_t* keys = kb[passes & 1];
-  k_rs_cstart<<<bdiv(n, 256), 256, 0, st>>>(keys, n, nc, L.cstart);
-  k_gather<<<bdiv(n, 256), 256, 0, st>>>(L.x, L.perm, n, *L.g, L.pos64, L.pos32, L.pos32lo, L.wrap);
+  *sorted_keys = kb[passes & 1];
+  return hipGetLastError();
+}
+
+hipError_t cell_starts(const uint32_t* sorted_keys, uint32_t n, uint32_t nc, uint32_t* cstart, hipStream_t st) {
+  if (n == 0) k_bfill_u32<<<bdiv(nc + 1, 256), 256, 0, st>>>(cstart, nc + 1, 0u);
+  else k_rs_cstart<<<bdiv(n, 256), 256, 0, st>>>(sorted_keys, n, nc, cstart);
+  return hipGetLastError();
+}
+
+hipError_t launch_build(const BuildLaunch& L, hipStream_t st) {
+  const uint32_t n = L.n, nc = L.ncells;
+  if (n > 0) k_cell_index<<<bdiv(n, 256), 256, 0, st>>>(L.x, n, *L.g, L.cell_of, L.err);
+  const uint32_t* keys = L.cell_of;
+  hipError_t e = radix_sort_cells(L.cell_of, L.rank, L.perm, L.rs_val, n, nc, L.rs_hist, L.rs_off, L.scan_tmp, &keys, st);
+  if (e == hipSuccess) e = cell_starts(keys, n, nc, L.cstart, st);
+  if (e != hipSuccess) return e;
+  if (n > 0) k_gather<<<bdiv(n, 256), 256, 0, st>>>(L.x, L.perm, n, *L.g, L.pos64, L.pos32, L.pos32lo, L.wrap);
   return hipGetLastError();
 }
 

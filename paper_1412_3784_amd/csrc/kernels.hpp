@@ -81,6 +81,15 @@ struct SweepLaunch {
 
 hipError_t launch_build(const BuildLaunch& L, hipStream_t st);
 uint32_t rs_tiles(uint32_t n);
+// Stable sort of n cell keys (all < nkeys) with their indices 0..n-1 (radix,
+// 8 bits per pass): the indices end in vals, *sorted_keys points at the sorted
+// keys (keys or keys_alt); hist and off hold rs_offsets(n) words, scan_tmp
+// rs_offsets(n) / 2048 + 2.
+hipError_t radix_sort_cells(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, uint32_t n,
+                            uint32_t nkeys, uint32_t* hist, uint32_t* off, uint32_t* scan_tmp,
+                            const uint32_t** sorted_keys, hipStream_t st);
+// cstart[c] = first sorted position with key >= c, c = 0..nc
+hipError_t cell_starts(const uint32_t* sorted_keys, uint32_t n, uint32_t nc, uint32_t* cstart, hipStream_t st);
 // largest of cstart[c + 1] - cstart[c] over c < nc into *out (statistics)
 hipError_t launch_max_occupancy(const uint32_t* cstart, uint32_t nc, uint32_t* out, hipStream_t st);
 size_t rs_offsets(uint32_t n);
