@@ -1,11 +1,12 @@
-// HIP kernels for gfx950: cell build (Sec. 4.1 / 4.2 of Dobson, Fox &
-// Saracino, arXiv:1412.3784: particles are assigned to cells at every step)
-// and the neighbourhood sweep that evaluates forces, energy and virial.
+// HIP kernels for gfx950: the neighbourhood sweep that evaluates forces,
+// energy and virial over the cell lists of Sec. 4.1 / 4.2 of Dobson, Fox &
+// Saracino, arXiv:1412.3784 (the cells are built every step by build.hip).
 //
 // Data layout in HBM (sorted = cell order, x fastest, particles of a cell by
 // ascending input index):
-//   cell_of[N], rank[N]    u32, input order      (bin_count)
-//   count[Nc], cstart[Nc+1] u32                  (histogram, exclusive scan)
+//   cell_of[N], rank[N]    u32, radix-sort keys (cell ids, ping-pong)
+//   rs_val[N]              u32, radix-sort values
+//   cstart[Nc+1]           u32, first sorted slot of each cell
 //   perm[N]                u32  sorted slot -> input index
 //   pos64[N]               double4 (x, y, z, -) wrapped FP64 position in the
 //                          variant's frame (Cartesian for DS, rotated for DO)
@@ -13,6 +14,7 @@
 //                          the FP64 centre of the particle's cell (high word)
 //   pos32lo[N]             float4 (ox, oy, oz, -): low word, offset - high
 //   wrap[N]                int4 lattice image of the wrap (debug only)
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
