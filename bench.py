@@ -83,6 +83,8 @@ def parse():
     p.add_argument("--deterministic", type=int, default=1, choices=[0, 1],
                    help="0: the autotuner may pick the half list (atomic sums)")
     p.add_argument("--replicas", type=int, default=None, help="batch/nemd: number of replicas")
+    p.add_argument("--skin", type=float, default=0.0,
+                   help="nemd: neighbour-list skin (0: cells rebuilt every step, graph-replayed)")
     p.add_argument("--no-batch", action="store_true", help="plain: skip the batched comparison")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-copy-probe", action="store_true")
@@ -345,14 +347,17 @@ def run_nemd(a, out):
     del xs
     bt = Batch(ns, 0, stream)
     bt.set_potential(boxes[0].pot)
+    if a.skin > 0:
+        bt.set_option(5, a.skin)                  # NCL_OPT_SKIN: neighbour lists
     bt.set_lattices("do", [b.L0 for b in boxes], [b.A for b in boxes], [b.t for b in boxes],
                     [b.automorphisms for b in boxes])
     bt.build_cells(x, "fp32")
     h = 0.002
-    bt.sllod_run(x, p, h, 1.0, a.warmup, use_graph=True)
+    graph = a.skin == 0
+    bt.sllod_run(x, p, h, 1.0, a.warmup, use_graph=graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    F, U, W, hist = bt.sllod_run(x, p, h, 1.0, a.steps, use_graph=True, history=True)
+    F, U, W, hist = bt.sllod_run(x, p, h, 1.0, a.steps, use_graph=graph, history=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = bt.stats()
@@ -366,13 +371,17 @@ def run_nemd(a, out):
     drift = np.abs(H - H[0] + work).max(axis=0) / np.abs(H[0])
     pairs = st["pairs"] / 2                       # pairs at the last step
     out.update({
-        "metric": "pair interactions/s (SLLOD step: bin + force + integrate, graph-replayed, FP32 forces)",
+        "metric": ("pair interactions/s (SLLOD step: bin + force + integrate, graph-replayed, FP32 forces)"
+                   if graph else
+                   f"pair interactions/s (SLLOD step: neighbour lists with skin {a.skin}, rebuilt when the "
+                   "skin bound or a remap requires, + force + integrate, FP32 forces)"),
         "value": pairs * a.steps / wall, "unit": "pairs/s", "steps": a.steps,
         "ms_per_step": 1e3 * wall / a.steps, "ns_per_particle_step": 1e9 * wall / (a.steps * ntot),
         "dtype": "f32 forces, f64 state and lattice",
         "config": {"workload": f"lj2.5_rho0.8_{len(boxes)}replicas_N{ntot}_sllod_h0.002",
                    "replicas": len(boxes), "n_total": ntot, "h": h},
         "energy_balance_rel_drift": {"max": float(drift.max()), "median": float(np.median(drift))},
+        "skin": a.skin, "list_rebuilds": st.get("list_rebuilds", 0),
         "pairs_note": "pairs/s uses the last step's pair count for every step",
     })
     return boxes

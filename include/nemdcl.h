@@ -85,6 +85,11 @@ extern "C" {
                                     applied to both particles with atomic sums
                                     (NCL_PREC_FP32 only; forces are then not
                                     bit-identical from run to run)               */
+#define NCL_OPT_SKIN 5           /* batches only: skin (in length units, default 0)
+                                    of the neighbour lists that
+                                    ncl_batch_sllod_run reuses between rebuilds;
+                                    0 rebuilds cells every step.  Set before
+                                    ncl_batch_set_lattices                        */
 #define NCL_OPT_DETERMINISTIC 4  /* 1 (default): the autotuner only picks
                                     schedules whose forces are bit-identical from
                                     run to run; 0: it may pick the half list.
@@ -113,6 +118,8 @@ typedef struct {
     float tune_ms[5];       /* autotuner timings of this workload class: per
                                particle, tiled with the three best-ranked
                                bricks, half list (-1: not timed)               */
+    int64_t list_rebuilds;  /* batches: neighbour-list builds of the last
+                               ncl_batch_sllod_run with a skin (0 otherwise)   */
 } ncl_stats;
 
 /* Create a handle on HIP device `device` that enqueues on `stream` (a
@@ -207,7 +214,7 @@ int ncl_batch_create(ncl_batch_handle *out, int device, void *stream, int32_t nr
 int ncl_batch_destroy(ncl_batch_handle b);
 /* As ncl_set_potential; call before ncl_batch_set_lattices. */
 int ncl_batch_set_potential(ncl_batch_handle b, double eps, double sigma, double rc, int shift_energy);
-/* NCL_OPT_DO_TIGHT and NCL_OPT_CLOSE_RADIUS only. */
+/* NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS and NCL_OPT_SKIN. */
 int ncl_batch_set_option(ncl_batch_handle b, int option, double value);
 /* Per replica r (host arrays): L0 + 9r, A + 9r (diagonal, traceless), strain
  * time t[r], naut[r] automorphisms at aut + 18r (as in ncl_set_lattice). */
@@ -234,7 +241,17 @@ int ncl_batch_get_lattices(ncl_batch_handle b, double *Lred, int32_t *cells);
  * use_graph != 0 one step is captured as a HIP graph and replayed nsteps
  * times.  hist (device, may be NULL) receives (nsteps + 1) x R records of 8
  * doubles: t, U, W_xx, W_yy, W_zz, K_xx, K_yy, K_zz with K = sum p p^T / m.
- * Afterwards the replicas' strain times have advanced by nsteps h. */
+ * Afterwards the replicas' strain times have advanced by nsteps h.
+ * With NCL_OPT_SKIN = s > 0, forces come from neighbour lists within
+ * d_cut + s, rebuilt only when a step could break them: between rebuilds at
+ * t_b and t (no remap) the lattice is E L(t_b), E = exp(A (t - t_b)), and
+ * positions E x(t_b) + delta, so the lists hold every pair within d_cut as
+ * long as max_k exp(-a_k (t - t_b)) (d_cut + 2 max|delta|) < d_cut + s; each
+ * step checks that (and remaps) on the device and reads one flag on the host,
+ * so steps are not graph-replayed; positions stay unwrapped between rebuilds
+ * and are put back into the reduced box at the end.  NCL_E_CAPACITY if a
+ * particle has more neighbours than the lists hold (1.5 times the mean of the
+ * densest replica plus 24, rounded up to a multiple of 4). */
 int ncl_batch_sllod_run(ncl_batch_handle b, double *x, double *p, void *F, double *U, double *W, double h,
                         double mass, int64_t nsteps, int use_graph, double *hist);
 const char *ncl_batch_last_error(ncl_batch_handle b);

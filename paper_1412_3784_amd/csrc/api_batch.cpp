@@ -30,6 +30,9 @@ struct ncl_batch {
   uint64_t ntot = 0, nslots = 0, ncells = 0;
   double eps = 1.0, sigma = 1.0, rc = 1.122462048309373, shift_on = 1.0, close_r = 0.45;
   int do_tight = 1, variant = NCL_DYNAMIC_OFFSET, precision = NCL_PREC_FP32, debug = 0;
+  double skin = 0.0;  // > 0: SLLOD reuses neighbour lists within d_cut + skin
+  uint32_t kmax = 0;
+  int64_t rebuilds = 0;  // list rebuilds of the last SLLOD run
   bool have_lattice = false, built = false;
   std::vector<double> t0;
   // device memory (one allocation per array)
@@ -46,6 +49,12 @@ struct ncl_batch {
   float4* pos32lo = nullptr;
   int4* wrap = nullptr;
   double* dbgF = nullptr;
+  int64_t *pcur = nullptr, *pb = nullptr;
+  uint2* vl = nullptr;
+  uint32_t* vl_cnt = nullptr;
+  double4* ysl = nullptr;
+  double *xb = nullptr, *tb = nullptr;
+  unsigned long long* dmax = nullptr;
   std::string err;
 };
 
@@ -77,6 +86,7 @@ static BatchDev view(ncl_batch* b) {
   D.variant = b->variant == NCL_DYNAMIC_OFFSET ? VAR_DO : VAR_DS;
   D.do_tight = b->do_tight;
   D.rc = b->rc;
+  D.rc_cells = b->rc + b->skin;
   D.n_off = b->n_off;
   D.slot_off = b->slot_off;
   D.cell_off = b->cell_off;
@@ -101,7 +111,17 @@ static BatchDev view(ncl_batch* b) {
   D.pos64 = b->pos64;
   D.pos32 = b->pos32;
   D.pos32lo = b->pos32lo;
-  D.wrap = b->debug ? b->wrap : nullptr;
+  D.wrap = (b->debug || b->skin > 0.0) ? b->wrap : nullptr;
+  D.pcur = b->pcur;
+  D.kmax = b->kmax;
+  D.vl = b->vl;
+  D.vl_cnt = b->vl_cnt;
+  D.ysl = b->ysl;
+  D.xb = b->xb;
+  D.tb = b->tb;
+  D.pb = b->pb;
+  D.dmax = b->dmax;
+  D.need = b->small + 11;
   D.kpart = b->kpart;
   return D;
 }
@@ -145,7 +165,9 @@ static void free_all(ncl_batch* b) {
   void* bufs[] = {b->n_off,  b->slot_off, b->cell_off, b->blk_rep, b->pol,     b->t0_d,    b->adiag,
                   b->lred,   b->kpart,    b->partial,  b->geom,    b->small,   b->cell_of, b->rank,
                   b->rep,    b->cstart,   b->scan_tmp, b->perm,   b->pos64,   b->pos32,   b->pos32lo,
-                  b->wrap,   b->dbgF,     b->rs_va,    b->rs_vb,   b->rs_hist, b->rs_off};
+                  b->wrap,   b->dbgF,     b->rs_va,    b->rs_vb,   b->rs_hist, b->rs_off,
+                  b->pcur,   b->pb,       b->vl,       b->ysl,     b->vl_cnt,  b->xb,
+                  b->tb,     b->dmax};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -201,6 +223,7 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->adiag, 3 * (size_t)nrep);
   if (e == hipSuccess) e = dalloc(&b->lred, 9 * (size_t)nrep);
   if (e == hipSuccess) e = dalloc(&b->geom, nrep);
+  if (e == hipSuccess) e = dalloc(&b->pcur, 2 * (size_t)nrep);
   if (e == hipSuccess) e = hipMemcpy(b->n_off, noff.data(), noff.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->slot_off, soff.data(), soff.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && !brep.empty()) e = hipMemcpy(b->blk_rep, brep.data(), brep.size() * 4, hipMemcpyHostToDevice);
@@ -249,6 +272,10 @@ int ncl_batch_set_option(ncl_batch_handle b, int option, double value) {
   } else if (option == NCL_OPT_CLOSE_RADIUS) {
     if (!(value >= 0.0)) return bfail(b, NCL_E_ARG, "close radius must be >= 0");
     b->close_r = value;
+  } else if (option == NCL_OPT_SKIN) {
+    if (!(value >= 0.0) || !isfinite(value)) return bfail(b, NCL_E_ARG, "skin must be >= 0");
+    if (b->have_lattice) return bfail(b, NCL_E_STATE, "set the skin before ncl_batch_set_lattices");
+    b->skin = value;
   } else {
     return bfail(b, NCL_E_ARG, "option not available for batches");
   }
@@ -295,6 +322,40 @@ int ncl_batch_set_lattices(ncl_batch_handle b, int variant, const double* L0, co
     b->ncells = ncells;
   }
   BCHK(b, hipMemcpy(b->cell_off, coff.data(), coff.size() * 4, hipMemcpyHostToDevice));
+  if (b->skin > 0.0) {
+    // list capacity: 1.5 times the mean count within d_cut + skin of the
+    // densest replica, plus 24 (a rebuild that needs more fails with
+    // NCL_E_CAPACITY)
+    const double rl = b->rc + b->skin;
+    double most = 0.0;
+    for (int r = 0; r < R; ++r)
+      most = fmax(most, (double)b->n[r] / fabs(mat_det(L0 + 9 * r)) * 4.0 / 3.0 * M_PI * rl * rl * rl);
+    const double km = 4.0 * ceil((1.5 * most + 24.0) / 4.0);  // entries come in groups of four
+    if (km * (double)b->nslots > 4.0e10 || b->nslots >= (1ull << 31))
+      return bfail(b, NCL_E_CAPACITY, "neighbour lists would not fit");
+    const uint32_t kmax = (uint32_t)km;
+    if (kmax != b->kmax || !b->vl) {
+      void* old[] = {b->vl, b->ysl, b->vl_cnt, b->xb, b->tb, b->pb, b->dmax};
+      for (void* q : old)
+        if (q) (void)hipFree(q);
+      b->vl = nullptr;
+      b->ysl = nullptr;
+      b->vl_cnt = nullptr;
+      b->xb = b->tb = nullptr;
+      b->pb = nullptr;
+      b->dmax = nullptr;
+      b->kmax = 0;
+      BCHK(b, dalloc(&b->vl, (size_t)kmax * b->nslots));
+      BCHK(b, dalloc(&b->ysl, b->nslots));
+      BCHK(b, dalloc(&b->vl_cnt, b->nslots));
+      BCHK(b, dalloc(&b->xb, 3 * b->ntot));
+      BCHK(b, dalloc(&b->tb, (size_t)R));
+      BCHK(b, dalloc(&b->pb, 2 * (size_t)R));
+      BCHK(b, dalloc(&b->dmax, (size_t)R));
+      b->kmax = kmax;
+    }
+    if (!b->wrap) BCHK(b, dalloc(&b->wrap, b->nslots));
+  }
   BCHK(b, hipMemcpy(b->pol, pol.data(), pol.size() * sizeof(RemapPolicy), hipMemcpyHostToDevice));
   BCHK(b, hipMemcpy(b->t0_d, t, (size_t)R * sizeof(double), hipMemcpyHostToDevice));
   BCHK(b, hipMemcpy(b->adiag, ad.data(), ad.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -361,6 +422,7 @@ int ncl_batch_get_stats(ncl_batch_handle b, ncl_stats* out) {
   out->pairs = (int64_t)s[1];
   out->fp64_pairs = (int64_t)s[2];
   out->neighbourhood = (int64_t)s[3];
+  out->list_rebuilds = b->rebuilds;
   out->max_occupancy = (int32_t)w[8];
   if (w[9]) {
     const int code = (int)w[9];
@@ -407,6 +469,63 @@ static hipError_t sllod_step(ncl_batch* b, const BatchDev& D, const SweepArgs& A
   return batch_observe(D, U, W, h, hist, hist_cap, true, st);
 }
 
+// SLLOD with neighbour lists (skin > 0): each step checks on the device
+// whether the lists still cover every pair within d_cut (skin bound and no
+// remap since the last rebuild), reads that one flag on the host and
+// rebuilds only when needed; positions stay unwrapped between rebuilds and
+// are put back into the reduced box at the end
+static int sllod_run_lists(ncl_batch* b, const BatchDev& D, const SweepArgs& A, double* x, double* p, void* F,
+                           double* U, double* W, double h, double mass, int64_t nsteps, double* hist,
+                           uint32_t hist_cap, hipStream_t st) {
+  const bool f64 = b->precision == NCL_PREC_FP64;
+  uint32_t* need_h = nullptr;
+  BCHK(b, hipHostMalloc((void**)&need_h, sizeof(uint32_t), hipHostMallocDefault));
+  auto read_need = [&](uint32_t* out) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(need_h, D.need, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    *out = *need_h;
+    return e;
+  };
+  int code = NCL_OK;
+  hipError_t e = hipSuccess;
+  uint32_t need = 0;
+  b->rebuilds = 0;
+  auto rebuild = [&](int off) -> int {
+    if ((e = hipMemsetAsync(D.need, 0, sizeof(uint32_t), st)) != hipSuccess) return bhip(b, e, "flag");
+    if ((e = batch_list_rebuild(D, x, off, h, st)) != hipSuccess) return bhip(b, e, "list rebuild");
+    if ((e = read_need(&need)) != hipSuccess) return bhip(b, e, "list rebuild");
+    if (need & 4u) return bfail(b, NCL_E_CAPACITY, "a particle has more neighbours than the lists hold");
+    ++b->rebuilds;
+    return NCL_OK;
+  };
+  if (e == hipSuccess) e = batch_prologue(D, 0, h, st);
+  if (e == hipSuccess) code = rebuild(0);
+  if (e == hipSuccess && code == NCL_OK) e = batch_list_force(A, D, x, b->precision, U, W, st);
+  if (e == hipSuccess && code == NCL_OK) e = batch_kick(D, p, F, f64, 0.0, mass, 1, st);
+  if (e == hipSuccess && code == NCL_OK) e = batch_observe(D, U, W, h, hist, hist_cap, false, st);
+  for (int64_t k = 0; k < nsteps && e == hipSuccess && code == NCL_OK; ++k) {
+    if ((e = batch_kick(D, p, F, f64, h, mass, 0, st)) != hipSuccess) break;
+    if ((e = batch_prologue(D, 1, h, st)) != hipSuccess) break;
+    if ((e = batch_drift(D, x, p, h, mass, st, false)) != hipSuccess) break;
+    if ((e = hipMemsetAsync(D.need, 0, sizeof(uint32_t), st)) != hipSuccess) break;
+    if ((e = batch_list_check(D, x, 1, h, b->skin, st)) != hipSuccess) break;
+    if ((e = read_need(&need)) != hipSuccess) break;
+    if (need && (code = rebuild(1)) != NCL_OK) break;
+    if ((e = batch_list_force(A, D, x, b->precision, U, W, st)) != hipSuccess) break;
+    if ((e = batch_kick(D, p, F, f64, h, mass, 1, st)) != hipSuccess) break;
+    e = batch_observe(D, U, W, h, hist, hist_cap, true, st);
+  }
+  // positions back into the reduced box, and cells that match them
+  if (e == hipSuccess && code == NCL_OK && D.n > 0) e = batch_wrap(D, x, st);
+  if (e == hipSuccess && code == NCL_OK) e = batch_build(D, x, st);
+  const hipError_t se = hipStreamSynchronize(st);
+  (void)hipHostFree(need_h);
+  if (code != NCL_OK) return code;
+  if (e != hipSuccess) return bhip(b, e, "sllod with neighbour lists");
+  if (se != hipSuccess) return bhip(b, se, "sllod with neighbour lists");
+  return NCL_OK;
+}
+
 int ncl_batch_sllod_run(ncl_batch_handle b, double* x, double* p, void* F, double* U, double* W, double h,
                         double mass, int64_t nsteps, int use_graph, double* hist) {
   if (!b || !x || !p || !F || !U || !W) return NCL_E_ARG;
@@ -425,6 +544,10 @@ int ncl_batch_sllod_run(ncl_batch_handle b, double* x, double* p, void* F, doubl
   const bool f64 = b->precision == NCL_PREC_FP64;
   // step counter to zero, forces and observables at the starting time
   BCHK(b, hipMemsetAsync(b->small + 10, 0, 4, st));
+  if (b->skin > 0.0) {
+    const int code = sllod_run_lists(b, D, A, x, p, F, U, W, h, mass, nsteps, hist, hist_cap, st);
+    if (code != NCL_OK) return code;
+  } else {
   BCHK(b, batch_prologue(D, 0, h, st));
   BCHK(b, batch_build(D, x, st));
   BCHK(b, batch_sweep(A, D, b->precision, false, U, W, st));
@@ -455,6 +578,7 @@ int ncl_batch_sllod_run(ncl_batch_handle b, double* x, double* p, void* F, doubl
     if (se != hipSuccess) return bhip(b, se, "graph replay");
   } else {
     for (int64_t k = 0; k < nsteps; ++k) BCHK(b, sllod_step(b, D, A, x, p, F, U, W, h, mass, hist, hist_cap, st));
+  }
   }
   // the caller's stream continues after the run
   BCHK(b, hipEventRecord(b->ev_out, st));

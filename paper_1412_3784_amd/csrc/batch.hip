@@ -51,8 +51,12 @@ __global__ void kb_prologue(BatchDev D, int off, double h) {
   int64_t coef[2], Mtot[9];
   remap_at(D.pol[r], t, Lred, coef);
   remap_matrix(D.pol[r], coef, Mtot);
+  if (D.pcur) {
+    D.pcur[2 * r] = coef[0];
+    D.pcur[2 * r + 1] = coef[1];
+  }
   CellGeom g;
-  const int rc = cell_geom_init(&g, Lred, Mtot, D.rc, D.variant, D.do_tight);
+  const int rc = cell_geom_init(&g, Lred, Mtot, D.rc_cells, D.variant, D.do_tight);
   int bad = 0;
   if (rc != GEOM_OK) {
     bad = rc == GEOM_E_SMALL ? 2 : 4;
@@ -153,8 +157,10 @@ __global__ void __launch_bounds__(SW_THREADS) kb_sweep(SweepArgs A0, BatchDev D)
 
 // per replica: U = 1/2 sum u, W = 1/2 sum w over its workgroups, in order;
 // DO rotates W back to Cartesian
+// cart: the partials are already Cartesian (neighbour-list forces), so the
+// dynamic-offset rotation back from the cell frame is skipped
 __global__ void kb_finalize(BatchDev D, const double* __restrict__ partial, double* __restrict__ U,
-                            double* __restrict__ W, unsigned long long* __restrict__ stats) {
+                            double* __restrict__ W, unsigned long long* __restrict__ stats, int cart) {
   __shared__ double red[4][PART_STRIDE];
   const uint32_t r = blockIdx.x;
   const uint32_t b0 = D.slot_off[r] / SW_THREADS, b1 = D.slot_off[r + 1] / SW_THREADS;
@@ -179,7 +185,7 @@ __global__ void kb_finalize(BatchDev D, const double* __restrict__ partial, doub
     U[r] = s[0];
     const double Wp[9] = {s[1], s[4], s[5], s[4], s[2], s[6], s[5], s[6], s[3]};
     double* Wr = W + 9 * (size_t)r;
-    if (g.variant == VAR_DO) {
+    if (g.variant == VAR_DO && !cart) {
       double T[9];
       for (int i = 0; i < 3; ++i)
         for (int c = 0; c < 3; ++c)
@@ -202,12 +208,21 @@ __global__ void kb_finalize(BatchDev D, const double* __restrict__ partial, doub
 // back into the reduced box after the drift (a lattice translation, which
 // leaves peculiar momenta unchanged).
 // ---------------------------------------------------------------------------
+// Per-particle kernels of the integrator walk the caller's order padded like
+// the slots: position u of replica r is input index n_off[r] + (u -
+// slot_off[r]) while that is below n_off[r+1], so loads and stores are
+// coalesced and a workgroup never straddles two replicas.
+__device__ inline uint32_t padded_input(const BatchDev& D, uint32_t u, uint32_t r) {
+  const uint32_t q = u - D.slot_off[r];
+  return (u < D.nslots && q < D.n_off[r + 1] - D.n_off[r]) ? D.n_off[r] + q : PAD_SLOT;
+}
+
 template <typename FT>
 __global__ void kb_kick(BatchDev D, double* __restrict__ p, const FT* __restrict__ F, double h, double mass,
                         int second) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = D.blk_rep[s / SW_THREADS];
-  const uint32_t i = (s < D.nslots) ? D.perm[s] : PAD_SLOT;
+  const uint32_t i = padded_input(D, s, r);
   double k2[3] = {0.0, 0.0, 0.0};
   if (i != PAD_SLOT) {
     const double* a = D.adiag + 3 * (size_t)r;
@@ -239,18 +254,35 @@ __global__ void kb_kick(BatchDev D, double* __restrict__ p, const FT* __restrict
   }
 }
 
-__global__ void kb_drift(BatchDev D, double* __restrict__ x, const double* __restrict__ p, double h, double mass) {
+__global__ void kb_drift(BatchDev D, double* __restrict__ x, const double* __restrict__ p, double h, double mass,
+                         int wrap) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.nslots) return;
-  const uint32_t i = D.perm[s];
-  if (i == PAD_SLOT) return;
   const uint32_t r = D.blk_rep[s / SW_THREADS];
+  // wrapping steps walk the padded input order; list steps walk the slots,
+  // whose Cartesian copy advances with them
+  const uint32_t i = wrap ? padded_input(D, s, r) : D.perm[s];
+  if (i == PAD_SLOT) return;
   const double* a = D.adiag + 3 * (size_t)r;
   double q[3];
   for (int d = 0; d < 3; ++d) {
     const double z = a[d] * h;
     const double phi1 = (z != 0.0) ? expm1(z) / z : 1.0;
     q[d] = exp(z) * x[3 * (size_t)i + d] + h * phi1 * p[3 * (size_t)i + d] / mass;
+  }
+  if (!wrap) {  // neighbour lists: positions stay unwrapped until the next rebuild
+    for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d];
+    // the slot-ordered copy takes the same affine step
+    const double4 y = D.ysl[s];
+    const double yv[3] = {y.x, y.y, y.z};
+    double yn[3];
+    for (int d = 0; d < 3; ++d) {
+      const double z = a[d] * h;
+      const double phi1 = (z != 0.0) ? expm1(z) / z : 1.0;
+      yn[d] = exp(z) * yv[d] + h * phi1 * p[3 * (size_t)i + d] / mass;
+    }
+    D.ysl[s] = make_double4(yn[0], yn[1], yn[2], 0.0);
+    return;
   }
   // back into the reduced box of the new lattice: q - Lred floor(Lred^-1 q)
   double Linv[9], L[9];
@@ -330,6 +362,252 @@ hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Verlet lists with a skin (neighbour lists reused between rebuilds).
+// Between two rebuilds at t_b and t no remap occurs, so the reduced lattice
+// is L(t) = E L(t_b) with E = exp(A (t - t_b)) (diagonal), and the unwrapped
+// positions are x(t) = E x(t_b) + delta.  A pair (i, j, m) then has
+// r(t) = E r(t_b) + delta_j - delta_i, so every pair closer than d_cut at t
+// was closer than d_cut + skin at t_b as long as
+//   max_k exp(-a_k (t - t_b)) (d_cut + 2 max|delta|) < d_cut + skin.
+// Entry k of slot s sits at ((k / 4) * nslots + s) * 4 + k % 4: a lane
+// appends to its own 32-byte group, and a wave reading group k / 4 of 64
+// consecutive slots reads one contiguous 2 KB block.  An entry is the
+// neighbour's slot and its lattice image m (three 10-bit biased components), with r = y_j - y_i + L m for the slot-ordered Cartesian
+// positions y, which are the wrapped positions at the rebuild advanced by the
+// same drift as the caller's positions (y - x stays a lattice vector).
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t pack_image(int m0, int m1, int m2) {
+  return ((uint32_t)(m0 + 512) & 0x3ffu) | (((uint32_t)(m1 + 512) & 0x3ffu) << 10) |
+         (((uint32_t)(m2 + 512) & 0x3ffu) << 20);
+}
+
+// positions into the current reduced box (input order)
+__global__ void kb_wrap(BatchDev D, double* __restrict__ x) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  const uint32_t r = find_rep(D.n_off, D.nrep, i);
+  double L[9], Linv[9];
+  for (int k = 0; k < 9; ++k) L[k] = D.lred[9 * (size_t)r + k];
+  mat_inv(L, Linv);
+  double q[3], n[3];
+  for (int d = 0; d < 3; ++d) q[d] = x[3 * (size_t)i + d];
+  if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) return;
+  for (int d = 0; d < 3; ++d) n[d] = floor(Linv[3 * d] * q[0] + Linv[3 * d + 1] * q[1] + Linv[3 * d + 2] * q[2]);
+  for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d] - (L[3 * d] * n[0] + L[3 * d + 1] * n[1] + L[3 * d + 2] * n[2]);
+}
+
+// neighbour lists within d_cut + skin (the cut-off the cells were built for),
+// from the FP64 wrapped positions, both directions of every pair
+template <int VAR>
+__global__ void __launch_bounds__(SW_THREADS) kb_list_build(BatchDev D) {
+  const uint32_t s = blockIdx.x * SW_THREADS + threadIdx.x;
+  if (s >= D.nslots) return;
+  const uint32_t r = D.blk_rep[s / SW_THREADS];
+  const uint32_t send = D.slot_off[r] + (D.n_off[r + 1] - D.n_off[r]);
+  if (s >= send) return;
+  const CellGeom& g = D.geom[r];
+  uint32_t cnt = 0;
+  const uint32_t kmax = D.kmax;
+  if (g.variant >= 0 && !(D.err[0] & 1)) {
+    const uint32_t cell0 = D.cell_off[r], pad = D.slot_off[r] - D.n_off[r];
+    const double rl2 = D.rc_cells * D.rc_cells;
+    const double4 pi = D.pos64[s];
+    const uint32_t hc = __float_as_uint(D.pos32[s].w);
+    // slot-ordered Cartesian position for the force passes
+    if (g.variant == VAR_DO) {
+      D.ysl[s] = make_double4(g.Q[0] * pi.x + g.Q[1] * pi.y + g.Q[2] * pi.z,
+                              g.Q[3] * pi.x + g.Q[4] * pi.y + g.Q[5] * pi.z,
+                              g.Q[6] * pi.x + g.Q[7] * pi.y + g.Q[8] * pi.z, 0.0);
+    } else {
+      D.ysl[s] = pi;
+    }
+    const int l0 = g.nc[0], l1 = g.nc[1], l2 = g.nc[2];
+    const int a = (int)(hc % (uint32_t)l0);
+    const int b = (int)((hc / (uint32_t)l0) % (uint32_t)l1);
+    const int c = (int)(hc / ((uint32_t)l0 * (uint32_t)l1));
+    // every slot of local cells [c0, c1) seen through image m
+    auto visit = [&](uint32_t c0, uint32_t c1, int m0, int m1, int m2) {
+      const double sx = g.B[0] * m0 + g.B[1] * m1 + g.B[2] * m2;
+      const double sy = g.B[3] * m0 + g.B[4] * m1 + g.B[5] * m2;
+      const double sz = g.B[6] * m0 + g.B[7] * m1 + g.B[8] * m2;
+      const double xo = pi.x - sx, yo = pi.y - sy, zo = pi.z - sz;
+      const bool zero = (m0 | m1 | m2) == 0;
+      const uint32_t st = D.cstart[cell0 + c0] + pad, en = D.cstart[cell0 + c1] + pad;
+      for (uint32_t js = st; js < en; ++js) {
+        if (zero && js == s) continue;
+        const double4 pj = D.pos64[js];
+        const double dx = pj.x - xo, dy = pj.y - yo, dz = pj.z - zo;
+        if (fma(dz, dz, fma(dy, dy, dx * dx)) < rl2) {
+          if (cnt < kmax) D.vl[(((size_t)(cnt >> 2) * D.nslots + s) << 2) + (cnt & 3u)] = make_uint2(js, pack_image(m0, m1, m2));
+          ++cnt;
+        }
+      }
+    };
+    if (VAR == VAR_DS) {
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int u[3] = {a + dx, b + dy, c + dz};
+            int m[3], w[3];
+            for (int k = 0; k < 3; ++k) {
+              m[k] = idiv_floor32(u[k], g.nc[k]);
+              w[k] = u[k] - m[k] * g.nc[k];
+            }
+            const uint32_t cj = (uint32_t)w[0] + (uint32_t)l0 * ((uint32_t)w[1] + (uint32_t)l1 * (uint32_t)w[2]);
+            visit(cj, cj + 1, m[0], m[1], m[2]);
+          }
+    } else {
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int C = c + dz;
+        const int k = idiv_floor32(C, l2);
+        const int cz = C - k * l2;
+        const double fy = -(double)k * g.B[5] / g.w[1];
+        const int B0 = (int)floor(b - g.grow[1] + fy);
+        const int B1 = (int)ceil(b + 1 + g.grow[1] + fy) - 1;
+        for (int Bq = B0; Bq <= B1; ++Bq) {
+          const int j = idiv_floor32(Bq, l1);
+          const int by = Bq - j * l1;
+          const double fx = -((double)j * g.B[1] + (double)k * g.B[2]) / g.w[0];
+          const int A0 = (int)floor(a - g.grow[0] + fx);
+          const int A1 = (int)ceil(a + 1 + g.grow[0] + fx) - 1;
+          const uint32_t rowbase = (uint32_t)l0 * ((uint32_t)by + (uint32_t)l1 * (uint32_t)cz);
+          for (int i = idiv_floor32(A0, l0); i <= idiv_floor32(A1, l0); ++i) {
+            const int axlo = max(A0 - i * l0, 0), axhi = min(A1 - i * l0, l0 - 1);
+            visit(rowbase + (uint32_t)axlo, rowbase + (uint32_t)axhi + 1, i, j, k);
+          }
+        }
+      }
+    }
+    if (cnt > kmax) atomicOr(D.need, 4u);
+  }
+  D.vl_cnt[s] = cnt < kmax ? cnt : kmax;
+}
+
+// largest |x - E x_b| per replica (slot order: a workgroup never straddles
+// two replicas; one atomic per workgroup on the replica's counter)
+__global__ void __launch_bounds__(SW_THREADS) kb_disp(BatchDev D, const double* __restrict__ x, int off, double h) {
+  __shared__ double red[SW_THREADS / 64];
+  const uint32_t s = blockIdx.x * SW_THREADS + threadIdx.x;
+  const uint32_t r = D.blk_rep[blockIdx.x];
+  const uint32_t i = padded_input(D, s, r);
+  double d = 0.0;
+  if (i != PAD_SLOT) {
+    const double dt = D.t0[r] + (double)(D.step[0] + off) * h - D.tb[r];
+    double e2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double u = x[3 * (size_t)i + k] - exp(D.adiag[3 * (size_t)r + k] * dt) * D.xb[3 * (size_t)i + k];
+      e2 = fma(u, u, e2);
+    }
+    d = sqrt(e2);
+    if (!(d == d)) d = 1e300;  // a non-finite position forces a rebuild (which flags it)
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_down(d, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < SW_THREADS / 64; ++w) d = fmax(d, red[w]);
+    atomicMax(&D.dmax[r], (unsigned long long)__double_as_longlong(d));
+  }
+}
+
+// per replica: does the skin still cover the interval since the last
+// rebuild, and has no remap occurred?  (bit 0: skin, bit 1: remap)
+__global__ void kb_need(BatchDev D, int off, double h, double skin) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D.nrep) return;
+  const double dt = D.t0[r] + (double)(D.step[0] + off) * h - D.tb[r];
+  double emax = 0.0;
+  for (int k = 0; k < 3; ++k) emax = fmax(emax, exp(-D.adiag[3 * (size_t)r + k] * dt));
+  const double dm = __longlong_as_double((long long)D.dmax[r]);
+  uint32_t need = 0;
+  if (!(emax * (D.rc + 2.0 * dm) < D.rc + skin)) need |= 1u;
+  if (D.pcur[2 * r] != D.pb[2 * r] || D.pcur[2 * r + 1] != D.pb[2 * r + 1]) need |= 2u;
+  if (need) atomicOr(D.need, need);
+}
+
+// record the state of a rebuild: positions, time and remap coefficients
+__global__ void kb_mark(BatchDev D, const double* __restrict__ x, int off, double h) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < 3 * (size_t)D.n) D.xb[i] = x[i];
+  if (i < D.nrep) {
+    D.tb[i] = D.t0[i] + (double)(D.step[0] + off) * h;
+    D.pb[2 * i] = D.pcur[2 * i];
+    D.pb[2 * i + 1] = D.pcur[2 * i + 1];
+  }
+}
+
+// forces, energy and virial from the lists at the current positions and
+// lattice; separations in FP64 from the slot-ordered positions.  Entries are
+// taken four at a time (their neighbour loads issued together), and the 27
+// lattice shifts L m with m in {-1,0,1}^3 come from LDS.
+template <int PREC>
+__global__ void __launch_bounds__(SW_THREADS) kb_list_force(SweepArgs A, BatchDev D, const double* __restrict__ x) {
+  __shared__ double shift[27][3];
+  const uint32_t lb = blockIdx.x;
+  const uint32_t r = D.blk_rep[lb];
+  const CellGeom& g = D.geom[r];
+  double L[9];
+  for (int k = 0; k < 9; ++k) L[k] = D.lred[9 * (size_t)r + k];
+  if (threadIdx.x < 27) {
+    const int m0 = (int)(threadIdx.x % 3) - 1, m1 = (int)((threadIdx.x / 3) % 3) - 1, m2 = (int)(threadIdx.x / 9) - 1;
+    for (int d = 0; d < 3; ++d) shift[threadIdx.x][d] = L[3 * d] * m0 + L[3 * d + 1] * m1 + L[3 * d + 2] * m2;
+  }
+  __syncthreads();
+  const uint32_t s = lb * SW_THREADS + threadIdx.x;
+  const uint32_t send = D.slot_off[r] + (D.n_off[r + 1] - D.n_off[r]);
+  Acc<PREC, false> acc;
+  if (s < send) {
+    if (g.variant >= 0 && !(D.err[0] & 1)) {
+      const double4 yi = D.ysl[s];
+      const uint32_t n = D.vl_cnt[s];
+      const uint4* grp = reinterpret_cast<const uint4*>(D.vl);
+      for (uint32_t k0 = 0; k0 < n; k0 += 4) {
+        // the group: two 16-byte loads, then up to four neighbour loads
+        const size_t gi = ((size_t)(k0 >> 2) * D.nslots + s) * 2;
+        const uint4 e01 = grp[gi], e23 = grp[gi + 1];
+        const uint32_t js[4] = {e01.x, e01.z, e23.x, e23.z}, mc[4] = {e01.y, e01.w, e23.y, e23.w};
+        double4 yj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) yj[u] = D.ysl[(k0 + u < n) ? js[u] : s];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (k0 + u >= n) break;
+          const int m0 = (int)(mc[u] & 0x3ffu) - 512, m1 = (int)((mc[u] >> 10) & 0x3ffu) - 512,
+                    m2 = (int)((mc[u] >> 20) & 0x3ffu) - 512;
+          double sx, sy, sz;
+          if (((unsigned)(m0 + 1) | (unsigned)(m1 + 1) | (unsigned)(m2 + 1)) <= 2u) {
+            const int q = (m0 + 1) + 3 * (m1 + 1) + 9 * (m2 + 1);
+            sx = shift[q][0];
+            sy = shift[q][1];
+            sz = shift[q][2];
+          } else {
+            sx = L[0] * m0 + L[1] * m1 + L[2] * m2;
+            sy = L[3] * m0 + L[4] * m1 + L[5] * m2;
+            sz = L[6] * m0 + L[7] * m1 + L[8] * m2;
+          }
+          const double dx = yj[u].x - yi.x + sx, dy = yj[u].y - yi.y + sy, dz = yj[u].z - yi.z + sz;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          acc.cand += 1;
+          if (r2 < A.rc2) {
+            if (PREC == 0 || r2 < A.rclose2_64)
+              pair64(acc, A.p64, dx, dy, dz, r2);
+            else
+              pair32(acc, A.p32, (float)dx, (float)dy, (float)dz, (float)r2);
+            acc.pairs += 1;
+          }
+        }
+      }
+    }
+    write_particle<VAR_DS, PREC, false>(A, g, s, acc);  // Cartesian frame: no rotation
+  }
+  double v[7];
+  acc_energy(acc, v);
+  const uint32_t st4[4] = {acc.cand, acc.pairs, 0u, 0u};
+  block_commit(A, lb, v, st4);
+}
+
 template <int VAR, int PREC, bool DEBUG>
 static void bsweep_t(const SweepArgs& A, const BatchDev& D, hipStream_t st) {
   kb_sweep<VAR, PREC, DEBUG><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
@@ -348,7 +626,7 @@ hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, boo
     NCL_BSW(VAR_DO, 0) NCL_BSW(VAR_DO, 1) NCL_BSW(VAR_DO, 2)
 #undef NCL_BSW
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats);
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0);
   return hipGetLastError();
 }
 
@@ -363,8 +641,9 @@ hipError_t batch_kick(const BatchDev& D, double* p, const void* F, bool f64, dou
   return hipGetLastError();
 }
 
-hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st) {
-  if (D.nslots) kb_drift<<<cdivb(D.nslots, 256), 256, 0, st>>>(D, x, p, h, mass);
+hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st,
+                       bool wrap) {
+  if (D.nslots) kb_drift<<<cdivb(D.nslots, 256), 256, 0, st>>>(D, x, p, h, mass, wrap ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -372,6 +651,46 @@ hipError_t batch_observe(const BatchDev& D, const double* U, const double* W, do
                          uint32_t hist_cap, bool advance, hipStream_t st) {
   if (advance) kb_step_advance<<<1, 64, 0, st>>>(D);
   kb_observe<<<D.nrep, 256, 0, st>>>(D, U, W, h, hist, hist_cap);
+  return hipGetLastError();
+}
+
+
+// Verlet lists: rebuild (wrap, cells for d_cut + skin, lists, mark) and the
+// per-step check; the caller reads D.need on the host between the two
+hipError_t batch_list_rebuild(const BatchDev& D, double* x, int off, double h, hipStream_t st) {
+  if (D.n > 0) kb_wrap<<<cdivb(D.n, 256), 256, 0, st>>>(D, x);
+  hipError_t e = batch_build(D, x, st);
+  if (e != hipSuccess) return e;
+  if (D.nslots) {
+    if (D.variant == VAR_DS) kb_list_build<VAR_DS><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D);
+    else kb_list_build<VAR_DO><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D);
+  }
+  const size_t nm = 3 * (size_t)D.n > D.nrep ? 3 * (size_t)D.n : D.nrep;
+  kb_mark<<<(uint32_t)((nm + 255) / 256), 256, 0, st>>>(D, x, off, h);
+  return hipGetLastError();
+}
+
+hipError_t batch_wrap(const BatchDev& D, double* x, hipStream_t st) {
+  if (D.n > 0) kb_wrap<<<cdivb(D.n, 256), 256, 0, st>>>(D, x);
+  return hipGetLastError();
+}
+
+hipError_t batch_list_check(const BatchDev& D, const double* x, int off, double h, double skin, hipStream_t st) {
+  kb_fill_u32<<<cdivb(2 * D.nrep, 256), 256, 0, st>>>((uint32_t*)D.dmax, 2 * D.nrep, 0u);
+  if (D.nslots) kb_disp<<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D, x, off, h);
+  kb_need<<<cdivb(D.nrep, 64), 64, 0, st>>>(D, off, h, skin);
+  return hipGetLastError();
+}
+
+hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, const double* x, int precision, double* U,
+                            double* W, hipStream_t st) {
+  kb_fill_u32<<<1, 64, 0, st>>>((uint32_t*)A.stats, 8, 0u);
+  if (D.nslots) {
+    if (precision == 0) kb_list_force<0><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D, x);
+    else if (precision == 2) kb_list_force<2><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D, x);
+    else kb_list_force<1><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D, x);
+  }
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 1);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ struct BatchDev {
   uint32_t nrep, n, nslots, ncells;
   int32_t variant, do_tight;
   double rc;
+  double rc_cells;           // cut-off the cells are built for: rc, or rc + skin with neighbour lists
   const uint32_t* n_off;     // [nrep+1] particles, input order
   const uint32_t* slot_off;  // [nrep+1] slots (multiples of the workgroup)
   const uint32_t* cell_off;  // [nrep+1] cell capacity offsets
@@ -31,6 +32,17 @@ struct BatchDev {
   float4* pos32lo;
   int4* wrap;                // debug only
   double* kpart;             // [nslots/256*3] kinetic partial sums
+  int64_t* pcur;             // [nrep*2] remap coefficients at the current time
+  // neighbour lists with a skin (entry k of slot s at k * nslots + s)
+  uint32_t kmax;
+  uint2* vl;                 // [nslots * kmax] (neighbour slot, packed image)
+  uint32_t* vl_cnt;
+  double4* ysl;              // [nslots] slot-ordered Cartesian positions (see batch.hip)
+  double* xb;                // positions at the last rebuild (input order)
+  double* tb;                // [nrep] time of the last rebuild
+  int64_t* pb;               // [nrep*2] remap coefficients at the last rebuild
+  unsigned long long* dmax;  // [nrep] largest peculiar displacement since (double bits)
+  uint32_t* need;            // rebuild flags: 1 skin, 2 remap, 4 list capacity
 };
 
 hipError_t batch_prologue(const BatchDev& D, int off, double h, hipStream_t st);
@@ -39,7 +51,13 @@ hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, boo
                        hipStream_t st);
 hipError_t batch_kick(const BatchDev& D, double* p, const void* F, bool f64, double h, double mass, int second,
                       hipStream_t st);
-hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st);
+hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st,
+                       bool wrap = true);
+hipError_t batch_wrap(const BatchDev& D, double* x, hipStream_t st);
+hipError_t batch_list_rebuild(const BatchDev& D, double* x, int off, double h, hipStream_t st);
+hipError_t batch_list_check(const BatchDev& D, const double* x, int off, double h, double skin, hipStream_t st);
+hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, const double* x, int precision, double* U,
+                            double* W, hipStream_t st);
 hipError_t batch_observe(const BatchDev& D, const double* U, const double* W, double h, double* hist,
                          uint32_t hist_cap, bool advance, hipStream_t st);
 

@@ -22,7 +22,7 @@ NCL_E_ARG, NCL_E_BOX_TOO_SMALL, NCL_E_LATTICE, NCL_E_CAPACITY = -1, -2, -3, -4
 NCL_E_HIP, NCL_E_DEVICE_FLAG, NCL_E_STATE = -5, -6, -7
 NCL_DYNAMIC_SIZE, NCL_DYNAMIC_OFFSET = 0, 1
 NCL_PREC_FP64, NCL_PREC_FP32, NCL_PREC_FP32_KAHAN = 0, 1, 2
-NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS, NCL_OPT_BAND, NCL_OPT_SWEEP, NCL_OPT_DETERMINISTIC = 0, 1, 2, 3, 4
+NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS, NCL_OPT_BAND, NCL_OPT_SWEEP, NCL_OPT_DETERMINISTIC, NCL_OPT_SKIN = 0, 1, 2, 3, 4, 5
 NCL_SWEEP_TILED, NCL_SWEEP_PARTICLE, NCL_SWEEP_AUTO, NCL_SWEEP_HALF = 0, 1, 2, 3
 
 VARIANTS = {"ds": NCL_DYNAMIC_SIZE, "do": NCL_DYNAMIC_OFFSET}
@@ -48,7 +48,7 @@ class ncl_stats(ctypes.Structure):
                 ("cells", ctypes.c_int32 * 3), ("max_occupancy", ctypes.c_int32), ("ncells", ctypes.c_int64),
                 ("candidates", ctypes.c_int64), ("pairs", ctypes.c_int64), ("fp64_pairs", ctypes.c_int64),
                 ("neighbourhood", ctypes.c_int64), ("sweep", ctypes.c_int32), ("brick", ctypes.c_int32 * 3),
-                ("tune_ms", ctypes.c_float * 5)]
+                ("tune_ms", ctypes.c_float * 5), ("list_rebuilds", ctypes.c_int64)]
 
 
 def _load():
@@ -186,7 +186,8 @@ def ncl_get_stats(h) -> dict:
     return {"n": s.n, "variant": s.variant, "precision": s.precision, "cells": list(s.cells),
             "max_occupancy": s.max_occupancy, "ncells": s.ncells, "candidates": s.candidates,
             "pairs": s.pairs, "fp64_pairs": s.fp64_pairs, "neighbourhood": s.neighbourhood,
-            "sweep": s.sweep, "brick": list(s.brick), "tune_ms": list(s.tune_ms)}
+            "sweep": s.sweep, "brick": list(s.brick), "tune_ms": list(s.tune_ms),
+            "list_rebuilds": s.list_rebuilds}
 
 
 def ncl_last_error(h) -> str:
@@ -322,7 +323,7 @@ def ncl_batch_get_stats(b) -> dict:
     _bcheck(b, _lib.ncl_batch_get_stats(b, ctypes.byref(s)))
     return {"n": s.n, "variant": s.variant, "precision": s.precision, "max_occupancy": s.max_occupancy,
             "ncells": s.ncells, "candidates": s.candidates, "pairs": s.pairs, "fp64_pairs": s.fp64_pairs,
-            "neighbourhood": s.neighbourhood}
+            "neighbourhood": s.neighbourhood, "list_rebuilds": s.list_rebuilds}
 
 
 def ncl_batch_get_lattices(b, nrep: int):
