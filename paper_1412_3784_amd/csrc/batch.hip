@@ -126,7 +126,7 @@ __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
 
 // one thread per slot; the workgroup's replica fixes the geometry
 template <int VAR, int PREC, bool DEBUG>
-__global__ void __launch_bounds__(SW_THREADS) kb_sweep(SweepArgs A0, BatchDev D) {
+__global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev D) {  // four waves per SIMD
   __shared__ float plist[PL_K * SW_THREADS_P * 3];
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t r = D.blk_rep[lb];

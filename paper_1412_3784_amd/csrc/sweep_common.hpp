@@ -153,7 +153,7 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 // Per-lane list of in-range separations waiting for evaluation (LDS,
 // entry e of lane t at base[(e * SW_THREADS + t) * 3]); evaluated by whole
 // waves so that no lane runs the pair code alone.
-constexpr int PL_K = 16;
+constexpr int PL_K = 12;
 constexpr int SW_THREADS_P = 256;
 struct PairList {
   float* base;
