@@ -130,7 +130,7 @@ def run_plain(a, out):
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    boxes = [wl.config2(k=k, n=a.n) for k in range(64)]
+    boxes = [wl.lj_uniaxial_strain(k=k, n=a.n) for k in range(64)]
     b0 = boxes[0]
     h = Handle(0, stream)
     h.set_potential(b0.pot)
@@ -314,7 +314,7 @@ def batch_measure(a, boxes, steps, loop_reps=3):
 
 
 def run_batch(a, out):
-    boxes = wl.config4(replicas=a.replicas or 512)
+    boxes = wl.wca_replica_batch(replicas=a.replicas or 512)
     r = batch_measure(a, boxes, a.steps)
     out.update({
         "metric": "pair interactions/s (batched bin + force over all replicas, FP32 offsets, 1e-5 force accuracy)",
@@ -337,7 +337,7 @@ def run_nemd(a, out):
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    boxes = wl.config5(replicas=a.replicas or 64)
+    boxes = wl.lj_sllod_batch(replicas=a.replicas or 64)
     xs = [b.positions(lattice_at(b, b.t)) for b in boxes]
     ns = [len(v) for v in xs]
     ntot = sum(ns)
@@ -474,7 +474,7 @@ def main():
     if a.workload == "plain":
         boxes = run_plain(a, out)
         if not a.no_batch:
-            r = batch_measure(a, wl.config4(replicas=a.replicas or 512), 20)
+            r = batch_measure(a, wl.wca_replica_batch(replicas=a.replicas or 512), 20)
             out["batched"] = {k: v for k, v in r.items() if k not in ("pairs", "cands", "t_force")}
             out["batched"]["workload"] = f"wca_rho0.8442_{r['replicas']}replicas_N{r['n_total']}_{a.variant}"
     elif a.workload == "batch":

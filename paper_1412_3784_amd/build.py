@@ -14,8 +14,10 @@ HEADERS = ["geometry.hpp", "kernels.hpp", "batch.hpp", "sweep_common.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-# FP contraction only where the source writes fma explicitly; no packed FP32
-# instructions.
+# FP contraction only where the source writes fma explicitly (the rounding of
+# every pair term is then fixed by the source); packed FP32 instructions are
+# switched off, since some of their forms have given occasional wrong results
+# on gfx950 without any error.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", CSRC, "-I", INCLUDE, "-Wno-unused-result"]

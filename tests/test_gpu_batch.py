@@ -30,7 +30,7 @@ def fits(box, variant):
 
 
 def small_batch(replicas=24, n_lo=300, n_hi=5000, variant="do"):
-    boxes = [b for b in wl.config4(replicas=replicas, n_lo=n_lo, n_hi=n_hi) if fits(b, variant)]
+    boxes = [b for b in wl.wca_replica_batch(replicas=replicas, n_lo=n_lo, n_hi=n_hi) if fits(b, variant)]
     assert len(boxes) >= replicas // 2
     return boxes
 
@@ -99,7 +99,7 @@ def test_batch_paper_do_rule_and_nondebug(variant):
 def test_batch_edge_sizes():
     """A one-particle replica, sizes at and around the 256-slot padding, and a
     flow-free replica in one batch."""
-    base = wl.config4(replicas=4, n_lo=600, n_hi=900)
+    base = wl.wca_replica_batch(replicas=4, n_lo=600, n_hi=900)
     boxes = [
         wl.make_box("planar", 0.3, 1, density=0.05, pot=wl.WCA, t_frac=0.2, seed=91, name="single"),
         wl.make_box("uniaxial", 0.4, 256, density=0.8442, pot=wl.WCA, t_frac=0.7, seed=92, name="n256"),
@@ -115,7 +115,7 @@ def test_batch_edge_sizes():
 
 
 def test_batch_single_replica_and_determinism():
-    boxes = [wl.config1()]
+    boxes = [wl.wca_planar_4096()]
     a = run_batch(boxes, "do", "fp32")
     check_replicas(boxes, a, "fp32", "single")
     b = run_batch(boxes, "do", "fp32")

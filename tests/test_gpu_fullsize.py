@@ -72,7 +72,7 @@ def check_sample(g, ref, idx, precision, label):
 def test_lj_1m_strain_sweep(k, variant):
     """1,048,576 LJ particles, uniaxial strain t_k = k T / 64 (the remap lies
     between k = 31 and 33); whole-box energy and virial against the oracle."""
-    box = wl.config2(k=k)
+    box = wl.lj_uniaxial_strain(k=k)
     x = oracle_positions(box)
     g = gpu_box(box, x, variant, "fp32", debug=True)
     Lr, Mt, _ = oracle.reduce(box.L0, box.A, box.t, box.automorphisms)
@@ -91,7 +91,7 @@ def test_lj_16m_grid_kahan(variant):
     """16,777,216 LJ particles (grid + jitter, biaxial, t = T/2), FP32 offsets
     with Kahan sums: sampled parity; total force ~ 0 (Newton's third law
     holds pair by pair in exact arithmetic)."""
-    box = wl.config3()
+    box = wl.lj_biaxial_grid()
     x = oracle_positions(box)
     g = gpu_box(box, x, variant, "fp32k", debug=True)
     Lr, Mt, _ = oracle.reduce(box.L0, box.A, box.t, box.automorphisms)
@@ -109,7 +109,7 @@ def test_wca_512_replica_batch():
     against the oracle (forces, digests, U, W)."""
     import torch
     from paper_1412_3784_amd import Batch
-    boxes = wl.config4()
+    boxes = wl.wca_replica_batch()
     xs = [oracle_positions(b) for b in boxes]
     bt = Batch([len(v) for v in xs])
     bt.set_potential(boxes[0].pot)
@@ -143,7 +143,7 @@ def test_lj_64_replica_sllod_shadow():
     for the smallest one."""
     import torch
     from paper_1412_3784_amd import Batch
-    boxes = wl.config5()
+    boxes = wl.lj_sllod_batch()
     ns = [len(b.frac) for b in boxes]
     xs = [b.positions(oracle.lattice_at(b.L0, b.A, b.t)) for b in boxes]
     ps = [wl.maxwell_momenta(n, 1.0, seed=5000 + r) for r, n in enumerate(ns)]

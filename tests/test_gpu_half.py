@@ -51,28 +51,28 @@ def test_half_tiny_boxes(flow, side, tf, variant):
 
 
 @pytest.mark.parametrize("variant", ["ds", "do"])
-def test_half_config1_wca_planar(variant):
+def test_half_wca_planar_4096(variant):
     """4,096 WCA particles at 1.2 per cell: a workgroup's 256 slots span
     more rows than get windows, so neighbour forces take the direct path."""
-    box = wl.config1()
+    box = wl.wca_planar_4096()
     x = oracle_positions(box)
     r = run_oracle(box, x)
     g = half(box, x, variant)
-    compare(g, r, "fp32", label=f"half/cfg1/{variant}")
+    compare(g, r, "fp32", label=f"half/wca4096/{variant}")
     assert g["stats"]["pairs"] == r.stats[1]
 
 
 @pytest.mark.parametrize("k", [0, 21, 31, 32, 33, 63])
 @pytest.mark.parametrize("variant", ["ds", "do"])
-def test_half_config2_strain_sweep_reduced_n(k, variant):
+def test_half_lj_uniaxial_strain_sweep_reduced_n(k, variant):
     """uniaxial LJ, 65,536 particles (13 per cell: windows in use) across
     the remap; the half list checks about half the candidates of the full
     per-particle sweep."""
-    box = wl.config2(k=k, n=65536)
+    box = wl.lj_uniaxial_strain(k=k, n=65536)
     x = oracle_positions(box)
     r = run_oracle(box, x)
     g = half(box, x, variant)
-    compare(g, r, "fp32", label=f"half/cfg2/k{k}/{variant}")
+    compare(g, r, "fp32", label=f"half/lj_uniaxial/k{k}/{variant}")
     assert g["stats"]["pairs"] == r.stats[1]
     full = run_gpu(box, x, variant, "fp32", debug=False, options={SWEEP_OPT: 1})
     ratio = g["stats"]["candidates"] / full["stats"]["candidates"]
@@ -91,13 +91,13 @@ def test_half_shear_lees_edwards(tf, variant):
 
 
 def test_half_grid_jitter_biaxial():
-    """config-3 construction (grid + jitter, biaxial, t = T/2) at 32^3."""
-    box = wl.config3(grid=32)
+    """the biaxial grid construction (grid + jitter, biaxial, t = T/2) at 32^3."""
+    box = wl.lj_biaxial_grid(grid=32)
     x = oracle_positions(box)
     r = run_oracle(box, x)
     for variant in ("ds", "do"):
         g = half(box, x, variant)
-        compare(g, r, "fp32", label=f"half/cfg3/{variant}")
+        compare(g, r, "fp32", label=f"half/lj_biaxial_grid/{variant}")
 
 
 def test_half_paper_neighbourhood_rule():
@@ -116,7 +116,7 @@ def test_half_repeat_and_autotuner():
     half list, and by default it does not."""
     import torch
     from paper_1412_3784_amd import Handle
-    box = wl.config2(k=40, n=65536)
+    box = wl.lj_uniaxial_strain(k=40, n=65536)
     x = oracle_positions(box)
     r = run_oracle(box, x, want_hash=False)
     a = half(box, x, "do", debug=False)

@@ -52,35 +52,35 @@ def test_tiny_boxes_all_precisions(flow, side, tf, variant):
 @pytest.mark.parametrize("sweep", SWEEPS)
 @pytest.mark.parametrize("variant", VARS)
 @pytest.mark.parametrize("prec", PRECS)
-def test_config1_wca_planar(variant, prec, sweep):
-    box = wl.config1()
+def test_wca_planar_4096(variant, prec, sweep):
+    box = wl.wca_planar_4096()
     x = oracle_positions(box)
     r = run_oracle(box, x)
     g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
-    compare(g, r, prec, label=f"cfg1/{variant}/{prec}/sweep{sweep}")
+    compare(g, r, prec, label=f"wca4096/{variant}/{prec}/sweep{sweep}")
     assert g["stats"]["pairs"] == r.stats[1]
 
 
 @pytest.mark.parametrize("k", [0, 9, 21, 31, 32, 33, 50, 63])
 @pytest.mark.parametrize("variant", VARS)
-def test_config2_strain_sweep_reduced_n(k, variant):
+def test_lj_uniaxial_strain_sweep_reduced_n(k, variant):
     """uniaxial LJ at 65,536 particles across the strain sweep (one remap)."""
-    box = wl.config2(k=k, n=65536)
+    box = wl.lj_uniaxial_strain(k=k, n=65536)
     x = oracle_positions(box)
     r = run_oracle(box, x)
     for sweep in SWEEPS:
         for prec in ("fp32", "fp64"):
             g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
-            compare(g, r, prec, label=f"cfg2/k{k}/{variant}/{prec}/sweep{sweep}")
+            compare(g, r, prec, label=f"lj_uniaxial/k{k}/{variant}/{prec}/sweep{sweep}")
 
 
-def test_config3_grid_jitter_reduced_n():
-    box = wl.config3(grid=32)
+def test_lj_biaxial_grid_jitter_reduced_n():
+    box = wl.lj_biaxial_grid(grid=32)
     x = oracle_positions(box)
     r = run_oracle(box, x)
     for variant in VARS:
         g = run_gpu(box, x, variant, "fp32k")
-        e = compare(g, r, "fp32k", label=f"cfg3/{variant}")
+        e = compare(g, r, "fp32k", label=f"lj_biaxial_grid/{variant}")
         assert e["rel_U"] < 1e-7
 
 
@@ -126,7 +126,7 @@ def test_do_paper_and_tight_neighbourhoods_agree():
 def test_deterministic_and_empty():
     import torch
     from paper_1412_3784_amd import Handle
-    box = wl.config2(k=20, n=50000)
+    box = wl.lj_uniaxial_strain(k=20, n=50000)
     x = oracle_positions(box)
     for variant in VARS:
         for prec in PRECS:
@@ -186,7 +186,7 @@ def test_autotuned_sweep_matches_oracle(variant):
     can pick meets the same parity bar (pair digests need the debug pass,
     which reuses the chosen schedule)."""
     from paper_1412_3784_amd import Handle, nemdcl
-    box = wl.config2(k=21, n=65536)
+    box = wl.lj_uniaxial_strain(k=21, n=65536)
     x = oracle_positions(box)
     r = run_oracle(box, x)
     h = Handle(0)

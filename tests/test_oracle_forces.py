@@ -89,7 +89,7 @@ def jittered_lattice(n_side, L, sigma, seed):
 
 
 def test_newton_third_law(orc):
-    box = wl.config1()
+    box = wl.wca_planar_4096()
     Lred, _, _ = orc.reduce(box.L0, box.A, box.t, box.automorphisms)
     x = jittered_lattice(16, Lred, 0.05, 5)
     r = orc.forces_cells(x, Lred, WCA)

@@ -127,7 +127,7 @@ def test_heights_cross_product(orc):
 def test_ds_counts_floor_of_heights(orc):
     L = np.diag([10.0, 20.0, 35.0])
     assert list(orc.ds_counts(L, 2.5)) == [4, 8, 14]
-    box = wl.config1()
+    box = wl.wca_planar_4096()
     # t = 0: a cube of side 16.929 with the WCA cut-off gives 15 cells per side
     assert list(orc.ds_counts(box.L0, wl.WCA_RC)) == [15, 15, 15]
 

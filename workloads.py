@@ -10,7 +10,8 @@ basis the *caller* supplies.  It contains none of the method's arithmetic: no
 lattice evolution or reduction, no cell binning, no distances or forces.  Both
 the FP64 oracle and the GPU library compute those on their own.
 
-Random numbers use numpy's PCG64 generator with seed 1000*config + replica.
+Random numbers use numpy's PCG64 generator with a fixed seed per workload
+and replica.
 """
 from __future__ import annotations
 
@@ -208,15 +209,15 @@ def make_box(flow: str, rate: float, n: int, *, density: Optional[float] = None,
 
 
 # ---------------------------------------------------------------------------
-# the five benchmark workloads
+# the benchmark workloads
 # ---------------------------------------------------------------------------
-def config1(seed_offset: int = 0) -> Box:
+def wca_planar_4096(seed_offset: int = 0) -> Box:
     """4,096 WCA particles, rho = 0.8442, planar elongation (rate 0.1), t = T/2, uniform."""
     return make_box("planar", 0.1, 4096, density=0.8442, pot=WCA, t_frac=0.5,
                     seed=1000 + seed_offset, name="wca_planar_4096")
 
 
-def config2(k: int = 32, n: int = 1 << 20) -> Box:
+def lj_uniaxial_strain(k: int = 32, n: int = 1 << 20) -> Box:
     """1,048,576 LJ (r_c = 2.5) particles, rho = 0.8, uniaxial (rate 0.5), uniform.
 
     Strain sweep t_k = k T / 64, k = 0..63, with the fractional coordinates fixed
@@ -225,14 +226,14 @@ def config2(k: int = 32, n: int = 1 << 20) -> Box:
                     seed=2000, name=f"lj_uniaxial_{n}_k{k}")
 
 
-def config3(grid: int = 256) -> Box:
+def lj_biaxial_grid(grid: int = 256) -> Box:
     """16,777,216 LJ particles, rho = 0.8, biaxial (rate 0.2), t = T/2; grid + 0.05 jitter."""
     n = grid ** 3
     return make_box("biaxial", 0.2, n, density=0.8, pot=LJ25, t_frac=0.5, seed=3000,
                     name=f"lj_biaxial_{n}", grid=grid, jitter_sigma=0.05)
 
 
-def config4(replicas: int = 512, n_lo: int = 2048, n_hi: int = 65536) -> List[Box]:
+def wca_replica_batch(replicas: int = 512, n_lo: int = 2048, n_hi: int = 65536) -> List[Box]:
     """512 WCA replicas (rho = 0.8442), N log-uniform in [n_lo, n_hi], random flow,
     rate uniform in [0.01, 1], t uniform in [0, T)."""
     out = []
@@ -247,7 +248,7 @@ def config4(replicas: int = 512, n_lo: int = 2048, n_hi: int = 65536) -> List[Bo
     return out
 
 
-def config5(replicas: int = 64, n_lo: int = 262144, n_hi: int = 2097152) -> List[Box]:
+def lj_sllod_batch(replicas: int = 64, n_lo: int = 262144, n_hi: int = 2097152) -> List[Box]:
     """64 LJ replicas (rho = 0.8), N log-uniform in [n_lo, n_hi] rounded to the
     nearest cube g^3, mixed flows, rate uniform in [0.05, 0.5], starting at
     t = 0 from a g^3 grid of sites with 0.05 Gaussian jitter (uniform random
