@@ -364,7 +364,9 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
     HIPCHK(h, hipMalloc((void**)&h->rank, m * sizeof(uint32_t)));
     HIPCHK(h, hipMalloc((void**)&h->perm, m * sizeof(uint32_t)));
     HIPCHK(h, hipMalloc((void**)&h->pos64, m * sizeof(double4)));
-    HIPCHK(h, hipMalloc((void**)&h->pos32, m * sizeof(float4)));
+    // four spare entries: the per-particle sweep reads candidates in groups
+    // of four and masks out those past a cell's run
+    HIPCHK(h, hipMalloc((void**)&h->pos32, (m + 4) * sizeof(float4)));
     HIPCHK(h, hipMalloc((void**)&h->pos32lo, m * sizeof(float4)));
     HIPCHK(h, hipMalloc((void**)&h->rs_val, m * sizeof(uint32_t)));
     h->cap_n = m;

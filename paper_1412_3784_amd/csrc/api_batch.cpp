@@ -206,7 +206,7 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->small, 16);
   if (e == hipSuccess) e = dalloc(&b->perm, slots);
   if (e == hipSuccess) e = dalloc(&b->pos64, slots);
-  if (e == hipSuccess) e = dalloc(&b->pos32, slots);
+  if (e == hipSuccess) e = dalloc(&b->pos32, slots + 4);  // + 4: groups of four candidate reads
   if (e == hipSuccess) e = dalloc(&b->pos32lo, slots);
   if (e == hipSuccess) e = dalloc(&b->cell_of, tot);
   if (e == hipSuccess) e = dalloc(&b->rank, tot);

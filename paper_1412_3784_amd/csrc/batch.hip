@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev
   const bool skip = g.variant < 0 || (D.err[0] & 1) != 0;
   if (s < send) {
     if (!skip) {
-      PairList L{plist + 3 * threadIdx.x, 0};
+      PairList L(plist + 3 * threadIdx.x);
       sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
     }
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);

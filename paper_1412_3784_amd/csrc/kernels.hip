@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, Cell
         for (uint32_t s = s0 + threadIdx.x; s < s1; s += SW_THREADS) {
           Acc<PREC, DEBUG> acc;
           uint32_t nbh = 0;
-          PairList L{plist + 3 * threadIdx.x, 0};
+          PairList L(plist + 3 * threadIdx.x);
           sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
           write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
           double v[7];
@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(SW_THREADS, 4) k_sweep_particle(SweepArgs A, C
   Acc<PREC, DEBUG> acc;
   uint32_t nbh = 0;
   if (s < A.n) {
-    PairList L{plist + 3 * threadIdx.x, 0};
+    PairList L(plist + 3 * threadIdx.x);
     sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
   }

@@ -84,9 +84,22 @@ __device__ inline void pair64(Acc<PREC, DEBUG>& acc, const Pot64& p, double dx, 
   const double s6 = s2 * s2 * s2;
   const double fs = r2i * s6 * (p.eps48 * s6 - p.eps24);
   const double phi = s6 * (p.eps4 * s6 - p.eps4) - p.shift;
-  acc.gx -= fs * dx;
-  acc.gy -= fs * dy;
-  acc.gz -= fs * dz;
+  if (PREC == 0) {
+    acc.gx -= fs * dx;
+    acc.gy -= fs * dy;
+    acc.gz -= fs * dz;
+  } else if (PREC == 2) {
+    kahan_add(acc.fx, acc.kx, (float)(-fs * dx));
+    kahan_add(acc.fy, acc.ky, (float)(-fs * dy));
+    kahan_add(acc.fz, acc.kz, (float)(-fs * dz));
+  } else {
+    // FP32 modes: the pair's force is rounded once and joins the FP32 sums
+    // (the tolerance is relative to sum_j |f_ij|, which holds this pair);
+    // the energy keeps an FP64 sum, its bound being 1e-7 of sum |u|
+    acc.fx += (float)(-fs * dx);
+    acc.fy += (float)(-fs * dy);
+    acc.fz += (float)(-fs * dz);
+  }
   acc.gu += phi;
   if (PREC == 0) {
     acc.gw[0] += fs * dx * dx;
@@ -152,22 +165,26 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 
 // Per-lane list of in-range separations waiting for evaluation (LDS,
 // entry e of lane t at base[(e * SW_THREADS + t) * 3]); evaluated by whole
-// waves so that no lane runs the pair code alone.
+// waves so that no lane runs the pair code alone.  `q` is the lane's next
+// free entry; the pairs are counted when the list is evaluated.
 constexpr int PL_K = 12;
 constexpr int SW_THREADS_P = 256;
+constexpr int PL_STRIDE = SW_THREADS_P * 3;
+typedef __attribute__((address_space(3))) float lds_float;  // 32-bit LDS pointer
 struct PairList {
-  float* base;
-  int cnt;
+  lds_float* base;
+  lds_float* q;
+  __device__ explicit PairList(float* p) : base((lds_float*)p), q((lds_float*)p) {}
 };
 
 template <int PREC, bool DEBUG>
 __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PairList& L) {
-  for (int e = 0; e < L.cnt; ++e) {
-    const float* q = L.base + e * (SW_THREADS_P * 3);
-    const float dx = q[0], dy = q[1], dz = q[2];
+  for (const lds_float* e = L.base; e != L.q; e += PL_STRIDE) {
+    const float dx = e[0], dy = e[1], dz = e[2];
     pair32(acc, A.p32, dx, dy, dz, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    acc.pairs += 1;
   }
-  L.cnt = 0;
+  L.q = L.base;
 }
 
 // Visit one neighbour cell `cj` seen through lattice image `m` (in the
@@ -213,13 +230,14 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
     // candidates' FP32 offsets are widened to FP64, so the separation is
     // exact up to the rounding of the stored FP32 offsets
     const double xo = oi[0] - dc[0], yo = oi[1] - dc[1], zo = oi[2] - dc[2];
-    // four candidate loads in flight per step (indices past the cell are
-    // clamped to its last particle and masked out)
-    for (uint32_t j0 = st; j0 < en; j0 += 4) {
-      const uint32_t jl = en - 1;
+    // four candidate loads in flight per step from one address; entries
+    // past the run (up to three; the array has four spare entries at its
+    // end) are read and masked out
+    const float4* pp = A.pos32 + st;
+    for (uint32_t j0 = st; j0 < en; j0 += 4, pp += 4) {
       float4 pj[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) pj[u] = A.pos32[min(j0 + u, jl)];
+      for (int u = 0; u < 4; ++u) pj[u] = pp[u];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const uint32_t j = j0 + u;
@@ -234,7 +252,10 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
             const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
             const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
             const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
-            const double xo64 = pi64.x - sx, yo64 = pi64.y - sy, zo64 = pi64.z - sz;
+            // the home position is re-read here rather than kept in
+            // registers through the loop (this path is rare)
+            const double4 ph64 = A.pos64[s];
+            const double xo64 = ph64.x - sx, yo64 = ph64.y - sy, zo64 = ph64.z - sz;
             const double4 pj64 = A.pos64[j];
             const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
             const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
@@ -248,16 +269,14 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
               debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
             }
           } else {
-            float* q = L.base + L.cnt * (SW_THREADS_P * 3);
-            q[0] = (float)dx;
-            q[1] = (float)dy;
-            q[2] = (float)dz;
-            L.cnt += 1;
-            acc.pairs += 1;
+            L.q[0] = (float)dx;
+            L.q[1] = (float)dy;
+            L.q[2] = (float)dz;
+            L.q += PL_STRIDE;
           }
         }
       }
-      if (__ballot(L.cnt > PL_K - 5) != 0) flush_list(acc, A, L);
+      if (__ballot(L.q > L.base + (PL_K - 5) * PL_STRIDE) != 0) flush_list(acc, A, L);
     }
   }
 }
@@ -349,13 +368,13 @@ __device__ inline void write_particle(const SweepArgs& A, const CellGeom& g, uin
   if (PREC == 0) {
     F[0] = acc.gx; F[1] = acc.gy; F[2] = acc.gz;
   } else if (PREC == 2) {
-    F[0] = ((double)acc.fx - (double)acc.kx) + acc.gx;
-    F[1] = ((double)acc.fy - (double)acc.ky) + acc.gy;
-    F[2] = ((double)acc.fz - (double)acc.kz) + acc.gz;
+    F[0] = (double)acc.fx - (double)acc.kx;
+    F[1] = (double)acc.fy - (double)acc.ky;
+    F[2] = (double)acc.fz - (double)acc.kz;
   } else {
-    F[0] = (double)acc.fx + acc.gx;
-    F[1] = (double)acc.fy + acc.gy;
-    F[2] = (double)acc.fz + acc.gz;
+    F[0] = (double)acc.fx;
+    F[1] = (double)acc.fy;
+    F[2] = (double)acc.fz;
   }
   double Fc[3];
   if (VAR == VAR_DO) {
