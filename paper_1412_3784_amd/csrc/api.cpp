@@ -43,8 +43,8 @@ struct ncl_ctx {
   const double* x = nullptr;
   CellGeom geom;
   // scratch
-  size_t cap_n = 0, cap_cells = 0, cap_scan = 0, cap_blocks = 0, cap_wrap = 0, cap_dbgF = 0;
-  uint32_t *cell_of = nullptr, *rank = nullptr, *cstart = nullptr, *perm = nullptr, *scan_tmp = nullptr,
+  size_t cap_n = 0, cap_cells = 0, cap_blocks = 0, cap_wrap = 0, cap_dbgF = 0;
+  uint32_t *cell_of = nullptr, *rank = nullptr, *cstart = nullptr, *perm = nullptr,
            *rs_val = nullptr, *rs_hist = nullptr, *rs_off = nullptr;
   size_t cap_rs = 0;
   double4* pos64 = nullptr;
@@ -133,7 +133,7 @@ int ncl_destroy(ncl_handle h) {
   int code = NCL_OK;
   if (h->small) {  // device state exists only after a build
     if (hipSetDevice(h->device) != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess) code = NCL_E_HIP;
-    void* bufs[] = {h->cell_of, h->rank,   h->cstart,  h->perm,     h->scan_tmp, h->pos64,
+    void* bufs[] = {h->cell_of, h->rank,   h->cstart,  h->perm,     h->pos64,
                     h->pos32,   h->pos32lo, h->wrap,  h->partial,  h->overflow, h->dbgF,
                     h->facc,    h->rs_val,  h->rs_hist, h->rs_off, h->small};
     for (void* b : bufs)
@@ -409,8 +409,6 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
       h->cap_bricks = nbr + 2;
     }
   }
-  const size_t nscan = rs_offsets((uint32_t)un) / 2048 + 2;
-  HIPCHK(h, grow(&h->scan_tmp, &h->cap_scan, nscan));
   if (precision == NCL_PREC_FP32 &&
       (h->sweep_mode == SWEEP_HALF || (h->sweep_mode == SWEEP_AUTO && !h->deterministic)))
     HIPCHK(h, grow(&h->facc, &h->cap_facc, 3 * un));
@@ -434,7 +432,6 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   L.rs_off = h->rs_off;
   L.cstart = h->cstart;
   L.perm = h->perm;
-  L.scan_tmp = h->scan_tmp;
   L.pos64 = h->pos64;
   L.pos32 = h->pos32;
   L.pos32lo = h->pos32lo;

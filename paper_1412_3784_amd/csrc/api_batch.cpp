@@ -43,7 +43,7 @@ struct ncl_batch {
   uint32_t* small = nullptr;  // [0..7] stats (4 u64), [8] maxocc, [9] err, [10] step
   uint32_t *rs_va = nullptr, *rs_vb = nullptr, *rs_hist = nullptr, *rs_off = nullptr;
   uint32_t *cell_of = nullptr, *rank = nullptr, *rep = nullptr, *cstart = nullptr,
-           *scan_tmp = nullptr, *perm = nullptr;
+           *perm = nullptr;
   double4* pos64 = nullptr;
   float4* pos32 = nullptr;
   float4* pos32lo = nullptr;
@@ -106,7 +106,6 @@ static BatchDev view(ncl_batch* b) {
   D.rs_hist = b->rs_hist;
   D.rs_off = b->rs_off;
   D.cstart = b->cstart;
-  D.scan_tmp = b->scan_tmp;
   D.perm = b->perm;
   D.pos64 = b->pos64;
   D.pos32 = b->pos32;
@@ -164,7 +163,7 @@ static void sweep_args(ncl_batch* b, SweepArgs* A, void* F) {
 static void free_all(ncl_batch* b) {
   void* bufs[] = {b->n_off,  b->slot_off, b->cell_off, b->blk_rep, b->pol,     b->t0_d,    b->adiag,
                   b->lred,   b->kpart,    b->partial,  b->geom,    b->small,   b->cell_of, b->rank,
-                  b->rep,    b->cstart,   b->scan_tmp, b->perm,   b->pos64,   b->pos32,   b->pos32lo,
+                  b->rep,    b->cstart,   b->perm,   b->pos64,   b->pos32,   b->pos32lo,
                   b->wrap,   b->dbgF,     b->rs_va,    b->rs_vb,   b->rs_hist, b->rs_off,
                   b->pcur,   b->pb,       b->vl,       b->ysl,     b->vl_cnt,  b->xb,
                   b->tb,     b->dmax};
@@ -215,7 +214,6 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->rs_vb, tot);
   if (e == hipSuccess) e = dalloc(&b->rs_hist, rs_offsets((uint32_t)tot));
   if (e == hipSuccess) e = dalloc(&b->rs_off, rs_offsets((uint32_t)tot));
-  if (e == hipSuccess) e = dalloc(&b->scan_tmp, rs_offsets((uint32_t)tot) / 2048 + 2);
   if (e == hipSuccess) e = dalloc(&b->partial, PART_STRIDE * (slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->kpart, 3 * (slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->pol, nrep);

@@ -352,7 +352,7 @@ hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
   if (D.n > 0) kb_cell_index<<<cdivb(D.n, 256), 256, 0, st>>>(D, x);
   const uint32_t* keys = D.cell_of;
   hipError_t e = radix_sort_cells(D.cell_of, D.rank, D.rs_va, D.rs_vb, D.n, D.ncells, D.rs_hist, D.rs_off,
-                                  D.scan_tmp, &keys, st);
+                                  &keys, st);
   if (e == hipSuccess) e = cell_starts(keys, D.n, D.ncells, D.cstart, st);
   if (e != hipSuccess) return e;
   if (D.n > 0) {

@@ -25,7 +25,7 @@ struct BatchDev {
   double* lred;              // [nrep*9] current reduced basis
   uint32_t* step;            // device step counter
   int* err;
-  uint32_t *cell_of, *rank, *rep, *cstart, *scan_tmp, *perm;
+  uint32_t *cell_of, *rank, *rep, *cstart, *perm;
   uint32_t *rs_va, *rs_vb, *rs_hist, *rs_off;  // radix sort of the cell keys
   double4* pos64;
   float4* pos32;

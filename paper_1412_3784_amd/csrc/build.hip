@@ -6,10 +6,11 @@
 // described at the top of kernels.hip.
 //
 // The permutation is a stable least-significant-digit radix sort of the
-// (cell, input index) pairs, 8 bits per pass: per tile of 2048 keys an LDS
-// histogram of the digit, one exclusive scan over (digit, tile), then a
-// scatter in which each key's rank among equal digits of its tile comes from
-// wave ballots.  Stability makes the order within a cell the input order, with
+// (cell, input index) pairs, in as few passes of at most 10 bits as the
+// largest cell index needs: per tile of 2048 keys an LDS histogram of the
+// digit, a scan of each digit's counts over the tiles, then a scatter in
+// which each key's rank among equal digits of its tile comes from wave
+// ballots.  Stability makes the order within a cell the input order, with
 // no atomics on global memory (scattered global atomics run at about 25 G/s
 // on MI355X, which bounded a count-and-scatter build).
 #include <hip/hip_runtime.h>
@@ -43,48 +44,94 @@ __global__ void k_cell_index(const double* __restrict__ x, uint32_t n, CellGeom 
   cell_of[i] = c;
 }
 
-// radix sort of the cell keys: RS_THREADS x RS_ITEMS keys per tile
+// radix sort of the cell keys: RS_THREADS x RS_ITEMS keys per tile; digits
+// of up to RS_MAXLOG bits (the passes split the key's bits evenly), kernels
+// instantiated for 2^8, 2^9 and 2^10 digit values
 constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 8;
 constexpr uint32_t RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int RS_MAXLOG = 10;
 
 // digit histogram of each tile -> hist[digit * ntiles + tile]
+template <int LOGND>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint32_t* __restrict__ key, uint32_t n, int shift,
-                                                       uint32_t* __restrict__ hist, uint32_t ntiles) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0u;
+                                                       uint32_t mask, uint32_t* __restrict__ hist, uint32_t ntiles) {
+  constexpr int ND = 1 << LOGND;
+  __shared__ uint32_t h[ND];
+  for (int d = threadIdx.x; d < ND; d += RS_THREADS) h[d] = 0u;
   __syncthreads();
   const uint32_t t0 = blockIdx.x * RS_TILE;
 #pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
     const uint32_t e = t0 + r * RS_THREADS + threadIdx.x;
-    if (e < n) atomicAdd(&h[(key[e] >> shift) & 255u], 1u);
+    if (e < n) atomicAdd(&h[(key[e] >> shift) & mask], 1u);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < ND; d += RS_THREADS) hist[(size_t)d * ntiles + blockIdx.x] = h[d];
+}
+
+// one block per digit: exclusive prefix of the digit's counts over the
+// tiles -> pre[digit * ntiles + tile], and the digit's total -> dtot[digit]
+__global__ void __launch_bounds__(RS_THREADS) k_rs_colscan(const uint32_t* __restrict__ hist, uint32_t ntiles,
+                                                          uint32_t* __restrict__ pre, uint32_t* __restrict__ dtot) {
+  const size_t row = (size_t)blockIdx.x * ntiles;
+  uint32_t carry = 0;
+  for (uint32_t t0 = 0; t0 < ntiles; t0 += RS_THREADS) {
+    const uint32_t t = t0 + threadIdx.x;
+    const uint32_t v = t < ntiles ? hist[row + t] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, &tot);
+    if (t < ntiles) pre[row + t] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
 // stable scatter of one digit pass: key e of the tile goes to
-// off[digit * ntiles + tile] + (number of earlier keys of the tile with the
-// same digit).  Keys are ranked in the order of e (rounds of 256, waves,
-// lanes; ties by wave ballots), staged in LDS in digit order, then written
-// out so that consecutive lanes store consecutive addresses of a digit's run.
-// vin == nullptr means the values are the indices e.
+// (keys of smaller digits) + (keys of its digit in earlier tiles) + (earlier
+// keys of the tile with the same digit).  Keys are ranked in the order of e
+// (rounds of 256, waves, lanes; ties by wave ballots), staged in LDS in digit
+// order, then written out so that consecutive lanes store consecutive
+// addresses of a digit's run.  vin == nullptr means the values are the
+// indices e.
+template <int LOGND>
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin, uint32_t n, int shift,
-                                                          const uint32_t* __restrict__ hist,
-                                                          const uint32_t* __restrict__ off, uint32_t ntiles,
+                                                          uint32_t mask, const uint32_t* __restrict__ hist,
+                                                          const uint32_t* __restrict__ pre,
+                                                          const uint32_t* __restrict__ dtot, uint32_t ntiles,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  __shared__ uint32_t off0[256], run[256], tstart[256];
-  __shared__ uint32_t wcnt[RS_THREADS / 64][256];
+  constexpr int ND = 1 << LOGND, DPT = ND / RS_THREADS;
+  __shared__ uint32_t off0[ND], run[ND], tstart[ND];
+  __shared__ uint32_t wcnt[RS_THREADS / 64][ND];
   __shared__ uint32_t sk[RS_TILE], sv[RS_TILE];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const uint32_t t0 = blockIdx.x * RS_TILE;
-  off0[tid] = off[(size_t)tid * ntiles + blockIdx.x];
-  uint32_t total;
-  tstart[tid] = block_excl_scan(hist[(size_t)tid * ntiles + blockIdx.x], &total);  // digit order
-  run[tid] = 0u;
-  for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0u;
+  // thread tid holds digits tid * DPT .. tid * DPT + DPT - 1: the digit's
+  // base (exclusive scan of the digit totals) and its start in the tile
+  // (exclusive scan of the tile's counts)
+  uint32_t dt[DPT], hc[DPT], sd = 0, sh = 0;
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int d = tid * DPT + q;
+    dt[q] = dtot[d];
+    hc[q] = hist[(size_t)d * ntiles + blockIdx.x];
+    sd += dt[q];
+    sh += hc[q];
+  }
+  uint32_t all, total;
+  uint32_t bd = block_excl_scan(sd, &all);
+  uint32_t bh = block_excl_scan(sh, &total);
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int d = tid * DPT + q;
+    off0[d] = bd + pre[(size_t)d * ntiles + blockIdx.x];
+    tstart[d] = bh;
+    run[d] = 0u;
+    for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][d] = 0u;
+    bd += dt[q];
+    bh += hc[q];
+  }
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
   for (int r = 0; r < RS_ITEMS; ++r) {
@@ -92,11 +139,11 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __res
     const bool valid = e < n;
     const uint32_t k = valid ? kin[e] : 0u;
     const uint32_t v = valid ? (vin ? vin[e] : e) : 0u;
-    const uint32_t d = (k >> shift) & 255u;
+    const uint32_t d = (k >> shift) & mask;
     // lanes of this wave holding the same digit
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < LOGND; ++bit) {
       const uint64_t bb = __ballot((d >> bit) & 1u);
       peers &= ((d >> bit) & 1u) ? bb : ~bb;
     }
@@ -110,19 +157,22 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __res
       sv[q] = v;
     }
     __syncthreads();
-    uint32_t add = 0;
-    for (int w = 0; w < RS_THREADS / 64; ++w) {
-      add += wcnt[w][tid];
-      wcnt[w][tid] = 0u;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int dd = tid * DPT + q;
+      uint32_t add = 0;
+      for (int w = 0; w < RS_THREADS / 64; ++w) {
+        add += wcnt[w][dd];
+        wcnt[w][dd] = 0u;
+      }
+      run[dd] += add;
     }
-    run[tid] += add;
     __syncthreads();
   }
   // the tile in digit order: slot q of digit d goes to off0[d] + q - tstart[d]
-  const uint32_t cnt = total;
-  for (uint32_t q = tid; q < cnt; q += RS_THREADS) {
+  for (uint32_t q = tid; q < total; q += RS_THREADS) {
     const uint32_t k = sk[q];
-    const uint32_t d = (k >> shift) & 255u;
+    const uint32_t d = (k >> shift) & mask;
     const uint32_t pos = off0[d] + (q - tstart[d]);
     kout[pos] = k;
     vout[pos] = sv[q];
@@ -158,57 +208,6 @@ __global__ void __launch_bounds__(1024) k_max_occ(const uint32_t* __restrict__ c
   }
 }
 
-// exclusive scan of u32 counts, three passes: per-block totals, a scan of
-// the totals in one block, then the per-block scan with its offset.
-constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
-
-__global__ void k_scan_totals(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ tot) {
-  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) s += (base + k < n) ? in[base + k] : 0u;
-  uint32_t total;
-  block_excl_scan(s, &total);
-  if (threadIdx.x == 0) tot[blockIdx.x] = total;
-}
-
-__global__ void k_scan_top(uint32_t* __restrict__ tot, uint32_t nb) {
-  // one block: exclusive scan of the block totals in place, in chunks
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < nb; base += SCAN_THREADS) {
-    const uint32_t i = base + threadIdx.x;
-    const uint32_t v = i < nb ? tot[i] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(v, &total);
-    if (i < nb) tot[i] = carry + ex;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += total;
-    __syncthreads();
-  }
-}
-
-__global__ void k_scan_apply(const uint32_t* __restrict__ in, uint32_t n, const uint32_t* __restrict__ tot,
-                             uint32_t* __restrict__ out) {
-  const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
-  uint32_t v[SCAN_ITEMS], s = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    v[k] = (base + k < n) ? in[base + k] : 0u;
-    s += v[k];
-  }
-  uint32_t total;
-  uint32_t run = tot[blockIdx.x] + block_excl_scan(s, &total);
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
-  }
-  if (base < n && base + SCAN_ITEMS >= n) out[n] = run;  // the thread holding the last element
-}
-
 __global__ void k_gather(const double* __restrict__ x, const uint32_t* __restrict__ perm, uint32_t n, CellGeom g,
                          double4* __restrict__ pos64, float4* __restrict__ pos32, float4* __restrict__ pos32lo,
                          int4* __restrict__ wrap) {
@@ -241,43 +240,49 @@ __global__ void k_gather(const double* __restrict__ x, const uint32_t* __restric
 // ---------------------------------------------------------------------------
 static inline uint32_t bdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
-// exclusive scan of n counts into out[0..n] (out[n] = total); tmp holds
-// ceil(n / SCAN_TILE) block totals
-static hipError_t scan_counts(const uint32_t* count, uint32_t n, uint32_t* tmp, uint32_t* out, hipStream_t st) {
-  const uint32_t nb = bdiv(n, SCAN_TILE);
-  if (nb == 0) return hipSuccess;
-  k_scan_totals<<<nb, SCAN_THREADS, 0, st>>>(count, n, tmp);
-  k_scan_top<<<1, SCAN_THREADS, 0, st>>>(tmp, nb);
-  k_scan_apply<<<nb, SCAN_THREADS, 0, st>>>(count, n, tmp, out);
-  return hipGetLastError();
-}
-
 hipError_t launch_max_occupancy(const uint32_t* cstart, uint32_t nc, uint32_t* out, hipStream_t st) {
   k_max_occ<<<1, 1024, 0, st>>>(cstart, nc, out);
   return hipGetLastError();
 }
 
-// tiles of the radix sort and the size of its (digit, tile) offset array
+// tiles of the radix sort and the size of its (digit, tile) arrays: the
+// histogram, and the per-tile prefixes followed by the digit totals
 uint32_t rs_tiles(uint32_t n) { return bdiv(n, RS_TILE); }
-size_t rs_offsets(uint32_t n) { return (size_t)256 * rs_tiles(n) + 1; }
+size_t rs_offsets(uint32_t n) { return ((size_t)rs_tiles(n) + 1) * (1u << RS_MAXLOG); }
+
+template <int LOGND>
+static void rs_pass(const uint32_t* kin, const uint32_t* vin, uint32_t n, int shift, uint32_t mask, uint32_t* hist,
+                    uint32_t* pre, uint32_t* dtot, uint32_t nt, uint32_t* kout, uint32_t* vout, hipStream_t st) {
+  k_rs_hist<LOGND><<<nt, RS_THREADS, 0, st>>>(kin, n, shift, mask, hist, nt);
+  k_rs_colscan<<<1u << LOGND, RS_THREADS, 0, st>>>(hist, nt, pre, dtot);
+  k_rs_scatter<LOGND><<<nt, RS_THREADS, 0, st>>>(kin, vin, n, shift, mask, hist, pre, dtot, nt, kout, vout);
+}
 
 hipError_t radix_sort_cells(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, uint32_t n,
-                            uint32_t nkeys, uint32_t* hist, uint32_t* off, uint32_t* scan_tmp,
-                            const uint32_t** sorted_keys, hipStream_t st) {
-  // 8-bit digits over the bits of the largest key
+                            uint32_t nkeys, uint32_t* hist, uint32_t* off, const uint32_t** sorted_keys,
+                            hipStream_t st) {
+  // the bits of the largest key, split evenly over the fewest passes of at
+  // most RS_MAXLOG bits (17 bits: two passes of 9)
   int bits = 1;
   while (bits < 32 && ((nkeys - 1u) >> bits) != 0u) ++bits;
-  const int passes = (bits + 7) / 8;
-  const uint32_t nt = rs_tiles(n), nh = 256u * nt;
+  const int passes = (bits + RS_MAXLOG - 1) / RS_MAXLOG;
+  const int db = (bits + passes - 1) / passes;
+  const uint32_t mask = (1u << db) - 1u;
+  const int logn = db < 8 ? 8 : db;
+  const uint32_t nt = rs_tiles(n);
+  uint32_t* pre = off;
+  uint32_t* dtot = off + (size_t)nt * (1u << RS_MAXLOG);
   // keys ping-pong between keys and keys_alt; values end in vals
   uint32_t* kb[2] = {keys, keys_alt};
   uint32_t* vb[2] = {(passes & 1) ? vals : vals_alt, (passes & 1) ? vals_alt : vals};
   for (int p = 0; p < passes && n > 0; ++p) {
-    k_rs_hist<<<nt, RS_THREADS, 0, st>>>(kb[p & 1], n, 8 * p, hist, nt);
-    const hipError_t e = scan_counts(hist, nh, scan_tmp, off, st);
-    if (e != hipSuccess) return e;
-    k_rs_scatter<<<nt, RS_THREADS, 0, st>>>(kb[p & 1], p ? vb[(p - 1) & 1] : nullptr, n, 8 * p, hist, off, nt,
-                                            kb[(p + 1) & 1], vb[p & 1]);
+    const uint32_t* vin = p ? vb[(p - 1) & 1] : nullptr;
+    if (logn == 8)
+      rs_pass<8>(kb[p & 1], vin, n, db * p, mask, hist, pre, dtot, nt, kb[(p + 1) & 1], vb[p & 1], st);
+    else if (logn == 9)
+      rs_pass<9>(kb[p & 1], vin, n, db * p, mask, hist, pre, dtot, nt, kb[(p + 1) & 1], vb[p & 1], st);
+    else
+      rs_pass<10>(kb[p & 1], vin, n, db * p, mask, hist, pre, dtot, nt, kb[(p + 1) & 1], vb[p & 1], st);
   }
   *sorted_keys = kb[passes & 1];
   return hipGetLastError();
@@ -293,7 +298,7 @@ hipError_t launch_build(const BuildLaunch& L, hipStream_t st) {
   const uint32_t n = L.n, nc = L.ncells;
   if (n > 0) k_cell_index<<<bdiv(n, 256), 256, 0, st>>>(L.x, n, *L.g, L.cell_of, L.err);
   const uint32_t* keys = L.cell_of;
-  hipError_t e = radix_sort_cells(L.cell_of, L.rank, L.perm, L.rs_val, n, nc, L.rs_hist, L.rs_off, L.scan_tmp, &keys, st);
+  hipError_t e = radix_sort_cells(L.cell_of, L.rank, L.perm, L.rs_val, n, nc, L.rs_hist, L.rs_off, &keys, st);
   if (e == hipSuccess) e = cell_starts(keys, n, nc, L.cstart, st);
   if (e != hipSuccess) return e;
   if (n > 0) k_gather<<<bdiv(n, 256), 256, 0, st>>>(L.x, L.perm, n, *L.g, L.pos64, L.pos32, L.pos32lo, L.wrap);

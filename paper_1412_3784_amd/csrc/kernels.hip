@@ -486,8 +486,8 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, Cell
 
 // one thread per particle in cell order, neighbour data straight from
 // global memory (L1/L2); partial sums per workgroup.  Four waves per SIMD
-// (at most 128 VGPRs, a few spilled; the 12-deep pair list keeps the LDS of
-// four workgroups per CU within 160 KB) hide more load latency than three:
+// (at most 128 VGPRs; the 13-deep pair list keeps the LDS of four
+// workgroups per CU within 160 KB) hide more load latency than three:
 // measured 0.80 -> 0.70 ms at 1 M LJ.
 template <int VAR, int PREC, bool DEBUG>
 __global__ void __launch_bounds__(SW_THREADS, 4) k_sweep_particle(SweepArgs A, CellGeom g) {

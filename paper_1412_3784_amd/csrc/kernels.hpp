@@ -58,8 +58,8 @@ struct BuildLaunch {
   const double* x;
   uint32_t n, ncells;
   // cell_of, rank: radix-sort keys (ping-pong); rs_val: values; rs_hist,
-  // rs_off: rs_offsets(n) words each; scan_tmp: scan block totals of rs_hist
-  uint32_t *cell_of, *rank, *rs_val, *rs_hist, *rs_off, *cstart, *perm, *scan_tmp;
+  // rs_off: rs_offsets(n) words each
+  uint32_t *cell_of, *rank, *rs_val, *rs_hist, *rs_off, *cstart, *perm;
   double4* pos64;
   float4* pos32;
   float4* pos32lo;
@@ -82,12 +82,11 @@ struct SweepLaunch {
 hipError_t launch_build(const BuildLaunch& L, hipStream_t st);
 uint32_t rs_tiles(uint32_t n);
 // Stable sort of n cell keys (all < nkeys) with their indices 0..n-1 (radix,
-// 8 bits per pass): the indices end in vals, *sorted_keys points at the sorted
-// keys (keys or keys_alt); hist and off hold rs_offsets(n) words, scan_tmp
-// rs_offsets(n) / 2048 + 2.
+// passes of at most 10 bits): the indices end in vals, *sorted_keys points at
+// the sorted keys (keys or keys_alt); hist and off hold rs_offsets(n) words.
 hipError_t radix_sort_cells(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, uint32_t n,
-                            uint32_t nkeys, uint32_t* hist, uint32_t* off, uint32_t* scan_tmp,
-                            const uint32_t** sorted_keys, hipStream_t st);
+                            uint32_t nkeys, uint32_t* hist, uint32_t* off, const uint32_t** sorted_keys,
+                            hipStream_t st);
 // cstart[c] = first sorted position with key >= c, c = 0..nc
 hipError_t cell_starts(const uint32_t* sorted_keys, uint32_t n, uint32_t nc, uint32_t* cstart, hipStream_t st);
 // largest of cstart[c + 1] - cstart[c] over c < nc into *out (statistics)

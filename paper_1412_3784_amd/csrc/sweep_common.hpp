@@ -167,7 +167,7 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 // entry e of lane t at base[(e * SW_THREADS + t) * 3]); evaluated by whole
 // waves so that no lane runs the pair code alone.  `q` is the lane's next
 // free entry; the pairs are counted when the list is evaluated.
-constexpr int PL_K = 12;
+constexpr int PL_K = 13;
 constexpr int SW_THREADS_P = 256;
 constexpr int PL_STRIDE = SW_THREADS_P * 3;
 typedef __attribute__((address_space(3))) float lds_float;  // 32-bit LDS pointer
@@ -276,7 +276,8 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
           }
         }
       }
-      if (__ballot(L.q > L.base + (PL_K - 5) * PL_STRIDE) != 0) flush_list(acc, A, L);
+      // the next group appends at most four entries per lane
+      if (__ballot(L.q > L.base + (PL_K - 4) * PL_STRIDE) != 0) flush_list(acc, A, L);
     }
   }
 }
