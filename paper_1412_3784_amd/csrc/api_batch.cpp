@@ -42,11 +42,10 @@ struct ncl_batch {
   CellGeom* geom = nullptr;
   uint32_t* small = nullptr;  // [0..7] stats (4 u64), [8] maxocc, [9] err, [10] step
   uint32_t *rs_va = nullptr, *rs_vb = nullptr, *rs_hist = nullptr, *rs_off = nullptr;
-  uint32_t *cell_of = nullptr, *rank = nullptr, *rep = nullptr, *cstart = nullptr,
+  uint32_t *cell_of = nullptr, *rank = nullptr, *cstart = nullptr,
            *perm = nullptr;
   double4* pos64 = nullptr;
   float4* pos32 = nullptr;
-  float4* pos32lo = nullptr;
   int4* wrap = nullptr;
   double* dbgF = nullptr;
   int64_t *pcur = nullptr, *pb = nullptr;
@@ -100,7 +99,6 @@ static BatchDev view(ncl_batch* b) {
   D.err = (int*)(b->small + 9);
   D.cell_of = b->cell_of;
   D.rank = b->rank;
-  D.rep = b->rep;
   D.rs_va = b->rs_va;
   D.rs_vb = b->rs_vb;
   D.rs_hist = b->rs_hist;
@@ -109,7 +107,6 @@ static BatchDev view(ncl_batch* b) {
   D.perm = b->perm;
   D.pos64 = b->pos64;
   D.pos32 = b->pos32;
-  D.pos32lo = b->pos32lo;
   D.wrap = (b->debug || b->skin > 0.0) ? b->wrap : nullptr;
   D.pcur = b->pcur;
   D.kmax = b->kmax;
@@ -135,7 +132,7 @@ static void sweep_args(ncl_batch* b, SweepArgs* A, void* F) {
   }
   A->pos64 = b->pos64;
   A->pos32 = b->pos32;
-  A->pos32lo = b->pos32lo;
+  A->pos32lo = nullptr;  // read by the single-box tiled sweep only
   A->cstart = b->cstart;
   A->perm = b->perm;
   A->wrap = b->wrap;
@@ -163,7 +160,7 @@ static void sweep_args(ncl_batch* b, SweepArgs* A, void* F) {
 static void free_all(ncl_batch* b) {
   void* bufs[] = {b->n_off,  b->slot_off, b->cell_off, b->blk_rep, b->pol,     b->t0_d,    b->adiag,
                   b->lred,   b->kpart,    b->partial,  b->geom,    b->small,   b->cell_of, b->rank,
-                  b->rep,    b->cstart,   b->perm,   b->pos64,   b->pos32,   b->pos32lo,
+                  b->cstart, b->perm,     b->pos64,    b->pos32,
                   b->wrap,   b->dbgF,     b->rs_va,    b->rs_vb,   b->rs_hist, b->rs_off,
                   b->pcur,   b->pb,       b->vl,       b->ysl,     b->vl_cnt,  b->xb,
                   b->tb,     b->dmax};
@@ -206,10 +203,8 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->perm, slots);
   if (e == hipSuccess) e = dalloc(&b->pos64, slots);
   if (e == hipSuccess) e = dalloc(&b->pos32, slots + 4);  // + 4: groups of four candidate reads
-  if (e == hipSuccess) e = dalloc(&b->pos32lo, slots);
   if (e == hipSuccess) e = dalloc(&b->cell_of, tot);
   if (e == hipSuccess) e = dalloc(&b->rank, tot);
-  if (e == hipSuccess) e = dalloc(&b->rep, tot);
   if (e == hipSuccess) e = dalloc(&b->rs_va, tot);
   if (e == hipSuccess) e = dalloc(&b->rs_vb, tot);
   if (e == hipSuccess) e = dalloc(&b->rs_hist, rs_offsets((uint32_t)tot));

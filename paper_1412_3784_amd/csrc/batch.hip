@@ -77,17 +77,27 @@ __global__ void kb_prologue(BatchDev D, int off, double h) {
 }
 
 __global__ void kb_cell_index(BatchDev D, const double* __restrict__ x) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  // the replica of the block's first particle by bisection, then a short
+  // forward step per thread (replicas hold far more particles than a block)
+  __shared__ uint32_t rb;
+  const uint32_t i0 = blockIdx.x * blockDim.x, i = i0 + threadIdx.x;
+  if (threadIdx.x == 0) rb = find_rep(D.n_off, D.nrep, i0);
+  __syncthreads();
   if (i >= D.n) return;
-  const uint32_t r = find_rep(D.n_off, D.nrep, i);
+  uint32_t r = rb;
+  while (r + 1 < D.nrep && D.n_off[r + 1] <= i) ++r;
   const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
   double xw[3];
   int32_t img[3];
   bool bad = false;
-  const uint32_t c = locate(D.geom[r], p, xw, img, &bad) + D.cell_off[r];
+  uint32_t c;
+  const uint32_t rf = __builtin_amdgcn_readfirstlane(r);
+  if (__ballot(r != rf) == 0)  // one replica in the wave: scalar geometry loads
+    c = locate(D.geom[rf], p, xw, img, &bad) + D.cell_off[rf];
+  else
+    c = locate(D.geom[r], p, xw, img, &bad) + D.cell_off[r];
   if (bad) atomicOr(D.err, 1);
   D.cell_of[i] = c;
-  D.rep[i] = r;
 }
 
 // sorted position s (replica-major, cells in order) -> slot in the
@@ -104,7 +114,9 @@ __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
   if (s >= D.nslots) return;
   const uint32_t i = D.perm[s];
   if (i == PAD_SLOT) return;
-  const uint32_t r = D.blk_rep[s / SW_THREADS];
+  // a block's slots belong to one replica: its geometry is read through
+  // scalar loads
+  const uint32_t r = __builtin_amdgcn_readfirstlane(D.blk_rep[s / SW_THREADS]);
   const CellGeom& g = D.geom[r];
   const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
   double xw[3];
@@ -120,7 +132,6 @@ __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
   const double o[3] = {xw[0] - cen[0], xw[1] - cen[1], xw[2] - cen[2]};
   const float hi[3] = {(float)o[0], (float)o[1], (float)o[2]};
   D.pos32[s] = make_float4(hi[0], hi[1], hi[2], __uint_as_float(c));
-  D.pos32lo[s] = make_float4((float)(o[0] - hi[0]), (float)(o[1] - hi[1]), (float)(o[2] - hi[2]), 0.f);
   if (D.wrap) D.wrap[s] = make_int4(img[0], img[1], img[2], 0);
 }
 

@@ -25,11 +25,10 @@ struct BatchDev {
   double* lred;              // [nrep*9] current reduced basis
   uint32_t* step;            // device step counter
   int* err;
-  uint32_t *cell_of, *rank, *rep, *cstart, *perm;
+  uint32_t *cell_of, *rank, *cstart, *perm;
   uint32_t *rs_va, *rs_vb, *rs_hist, *rs_off;  // radix sort of the cell keys
   double4* pos64;
   float4* pos32;
-  float4* pos32lo;
   int4* wrap;                // debug only
   double* kpart;             // [nslots/256*3] kinetic partial sums
   int64_t* pcur;             // [nrep*2] remap coefficients at the current time
