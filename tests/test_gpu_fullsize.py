@@ -86,6 +86,24 @@ def test_lj_1m_strain_sweep(k, variant):
     print(f"lj1M k={k} {variant}: max {mx:.2e} rms {rms:.2e}")
 
 
+def test_lj_4m_ten_bit_radix():
+    """4,194,304 LJ particles, uniaxial strain t = 40 T / 64, dynamic offset:
+    326,040 cells, so the cell keys have 19 bits and the build sorts them in
+    two passes of 10-bit digits (the other workloads use 7-, 8- and 9-bit
+    digits).  Sampled pair sets and forces against the oracle; every particle
+    has a pair count (the permutation misses none)."""
+    box = wl.lj_uniaxial_strain(k=40, n=1 << 22)
+    x = oracle_positions(box)
+    g = gpu_box(box, x, "do", "fp32", debug=True)
+    assert (1 << 18) < g["stats"]["ncells"] <= (1 << 20), g["stats"]["ncells"]
+    Lr, Mt, _ = oracle.reduce(box.L0, box.A, box.t, box.automorphisms)
+    idx = sample_idx(len(x), 4096, 41)
+    ref = oracle.forces_cells(x, Lr, box.pot, Mkey=Mt, subset=idx)
+    mx, rms = check_sample(g, ref, idx, "fp32", "lj4M/do")
+    assert g["count"].sum() == g["stats"]["pairs"] and g["count"].min() > 0
+    print(f"lj4M do: max {mx:.2e} rms {rms:.2e}")
+
+
 @pytest.mark.parametrize("variant", ["do", "ds"])
 def test_lj_16m_grid_kahan(variant):
     """16,777,216 LJ particles (grid + jitter, biaxial, t = T/2), FP32 offsets
