@@ -10,9 +10,11 @@
 //   perm[N]                u32  sorted slot -> input index
 //   pos64[N]               double4 (x, y, z, -) wrapped FP64 position in the
 //                          variant's frame (Cartesian for DS, rotated for DO)
-//   pos32[N]               float4 (ox, oy, oz, cell id bits): FP32 offset from
-//                          the FP64 centre of the particle's cell (high word)
+//   pos32[N + 4]           float4 (ox, oy, oz, cell id bits): FP32 offset from
+//                          the FP64 centre of the particle's cell (high word);
+//                          four spare entries for reads past a run's end
 //   pos32lo[N]             float4 (ox, oy, oz, -): low word, offset - high
+//                          (read by the tiled sweep only)
 //   wrap[N]                int4 lattice image of the wrap (debug only)
 
 #include <hip/hip_runtime.h>
