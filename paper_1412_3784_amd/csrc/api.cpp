@@ -376,7 +376,7 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
     if (h->cstart) HIPCHK(h, hipFree(h->cstart));
     h->cstart = nullptr;
     h->cap_cells = 0;
-    HIPCHK(h, hipMalloc((void**)&h->cstart, want_cells * sizeof(uint32_t)));
+    HIPCHK(h, hipMalloc((void**)&h->cstart, cstart_words((uint32_t)(want_cells - 1)) * sizeof(uint32_t)));
     h->cap_cells = want_cells;
   }
   // radix sort of the cell keys: (digit, tile) counts and offsets

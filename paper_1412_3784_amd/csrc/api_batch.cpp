@@ -310,7 +310,7 @@ int ncl_batch_set_lattices(ncl_batch_handle b, int variant, const double* L0, co
     if (b->cstart) (void)hipFree(b->cstart);
     if (b->cell_off) (void)hipFree(b->cell_off);
     b->cstart = b->cell_off = nullptr;
-    BCHK(b, dalloc(&b->cstart, ncells + 1));
+    BCHK(b, dalloc(&b->cstart, cstart_words((uint32_t)ncells)));
     BCHK(b, dalloc(&b->cell_off, (size_t)R + 1));
     b->ncells = ncells;
   }

@@ -81,6 +81,7 @@ __global__ void kb_cell_index(BatchDev D, const double* __restrict__ x) {
   // forward step per thread (replicas hold far more particles than a block)
   __shared__ uint32_t rb;
   const uint32_t i0 = blockIdx.x * blockDim.x, i = i0 + threadIdx.x;
+  if (i == 0) D.cstart[D.ncells + 1] = 0u;  // no runs of empty cells queued yet
   if (threadIdx.x == 0) rb = find_rep(D.n_off, D.nrep, i0);
   __syncthreads();
   if (i >= D.n) return;
@@ -365,6 +366,9 @@ hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
   hipError_t e = radix_sort_cells(D.cell_of, D.rank, D.rs_va, D.rs_vb, D.n, D.ncells, D.rs_hist, D.rs_off,
                                   &keys, st);
   if (e == hipSuccess) e = cell_starts(keys, D.n, D.ncells, D.cstart, st);
+  // the replicas' unused cell ranges: one queued run each, filled by a
+  // launch of their own (measured faster here than inside kb_gather)
+  if (e == hipSuccess) e = fill_empty_runs(D.cstart, D.ncells, st);
   if (e != hipSuccess) return e;
   if (D.n > 0) {
     kb_place<<<cdivb(D.n, 256), 256, 0, st>>>(D, keys);

@@ -32,8 +32,9 @@ __global__ void k_bfill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v) {
 // binning
 // ---------------------------------------------------------------------------
 __global__ void k_cell_index(const double* __restrict__ x, uint32_t n, CellGeom g, uint32_t* __restrict__ cell_of,
-                             int* __restrict__ err) {
+                             int* __restrict__ err, uint32_t* __restrict__ cs_runs) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *cs_runs = 0u;  // no runs of empty cells queued yet (k_rs_cstart)
   if (i >= n) return;
   const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
   double xw[3];
@@ -180,16 +181,45 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint32_t* __res
 }
 
 // cell starts from the sorted keys: cstart[c] = first slot whose key is >= c
-// (empty cells get the start of the next occupied one; cstart[nc] = n)
+// (empty cells get the start of the next occupied one; cstart[nc] = n).  The
+// first particle of each occupied cell writes its cell and the empty cells
+// before it; a run of more than CS_SPAN empty cells (the unused cell range of
+// a batched replica, or a sparse box) is queued instead, as (first cell,
+// length, value) after cstart[nc], and filled by a later kernel
+// (cs_fill_runs: one workgroup per run; one thread writing a run of
+// thousands of cells held the whole build).  Such runs are disjoint and
+// longer than CS_SPAN, so at most nc / CS_SPAN + 1 of them exist.
+constexpr uint32_t CS_SPAN = 64;
+
+__device__ inline void cs_fill(uint32_t* __restrict__ cstart, uint32_t* __restrict__ runs, uint32_t c0, uint32_t c1,
+                               uint32_t v) {  // cells c0 .. c1 - 1
+  if (c1 <= c0) return;
+  if (c1 - c0 <= CS_SPAN) {
+    for (uint32_t c = c0; c < c1; ++c) cstart[c] = v;
+  } else {
+    const uint32_t q = atomicAdd(runs, 1u);
+    runs[1 + 3 * q] = c0;
+    runs[2 + 3 * q] = c1 - c0;
+    runs[3 + 3 * q] = v;
+  }
+}
+
 __global__ void k_rs_cstart(const uint32_t* __restrict__ key, uint32_t n, uint32_t nc, uint32_t* __restrict__ cstart) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
+  uint32_t* runs = cstart + nc + 1;
   const uint32_t k = key[s];
   const uint32_t c0 = (s == 0) ? 0u : key[s - 1] + 1u;
-  for (uint32_t c = c0; c <= k; ++c) cstart[c] = s;
-  if (s == n - 1)
-    for (uint32_t c = k + 1; c <= nc; ++c) cstart[c] = n;
+  if (c0 <= k) {
+    cstart[k] = s;
+    cs_fill(cstart, runs, c0, k, s);
+  }
+  if (s == n - 1) {
+    cstart[nc] = n;
+    cs_fill(cstart, runs, k + 1, nc, n);
+  }
 }
+
 
 // largest cell occupancy, for the statistics only (one block: a counter
 // updated by every wave of a launch serialises in one L2 channel)
@@ -210,7 +240,8 @@ __global__ void __launch_bounds__(1024) k_max_occ(const uint32_t* __restrict__ c
 
 __global__ void k_gather(const double* __restrict__ x, const uint32_t* __restrict__ perm, uint32_t n, CellGeom g,
                          double4* __restrict__ pos64, float4* __restrict__ pos32, float4* __restrict__ pos32lo,
-                         int4* __restrict__ wrap) {
+                         int4* __restrict__ wrap, uint32_t* __restrict__ cstart, uint32_t nc) {
+  cs_fill_runs(cstart, nc);
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const uint32_t i = perm[s];
@@ -288,6 +319,15 @@ hipError_t radix_sort_cells(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, 
   return hipGetLastError();
 }
 
+__global__ void k_cs_runs(uint32_t* __restrict__ cstart, uint32_t nc) { cs_fill_runs(cstart, nc); }
+
+hipError_t fill_empty_runs(uint32_t* cstart, uint32_t nc, hipStream_t st) {
+  k_cs_runs<<<512, 256, 0, st>>>(cstart, nc);
+  return hipGetLastError();
+}
+
+size_t cstart_words(uint32_t nc) { return (size_t)nc + 1 + 1 + 3 * ((size_t)nc / CS_SPAN + 2); }
+
 hipError_t cell_starts(const uint32_t* sorted_keys, uint32_t n, uint32_t nc, uint32_t* cstart, hipStream_t st) {
   if (n == 0) k_bfill_u32<<<bdiv(nc + 1, 256), 256, 0, st>>>(cstart, nc + 1, 0u);
   else k_rs_cstart<<<bdiv(n, 256), 256, 0, st>>>(sorted_keys, n, nc, cstart);
@@ -296,12 +336,13 @@ hipError_t cell_starts(const uint32_t* sorted_keys, uint32_t n, uint32_t nc, uin
 
 hipError_t launch_build(const BuildLaunch& L, hipStream_t st) {
   const uint32_t n = L.n, nc = L.ncells;
-  if (n > 0) k_cell_index<<<bdiv(n, 256), 256, 0, st>>>(L.x, n, *L.g, L.cell_of, L.err);
+  if (n > 0) k_cell_index<<<bdiv(n, 256), 256, 0, st>>>(L.x, n, *L.g, L.cell_of, L.err, L.cstart + nc + 1);
   const uint32_t* keys = L.cell_of;
   hipError_t e = radix_sort_cells(L.cell_of, L.rank, L.perm, L.rs_val, n, nc, L.rs_hist, L.rs_off, &keys, st);
   if (e == hipSuccess) e = cell_starts(keys, n, nc, L.cstart, st);
   if (e != hipSuccess) return e;
-  if (n > 0) k_gather<<<bdiv(n, 256), 256, 0, st>>>(L.x, L.perm, n, *L.g, L.pos64, L.pos32, L.pos32lo, L.wrap);
+  if (n > 0)
+    k_gather<<<bdiv(n, 256), 256, 0, st>>>(L.x, L.perm, n, *L.g, L.pos64, L.pos32, L.pos32lo, L.wrap, L.cstart, nc);
   return hipGetLastError();
 }
 

@@ -87,8 +87,14 @@ uint32_t rs_tiles(uint32_t n);
 hipError_t radix_sort_cells(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, uint32_t n,
                             uint32_t nkeys, uint32_t* hist, uint32_t* off, const uint32_t** sorted_keys,
                             hipStream_t st);
-// cstart[c] = first sorted position with key >= c, c = 0..nc
+// cstart[c] = first sorted position with key >= c, c = 0..nc; cstart holds
+// cstart_words(nc) words (the cell starts, then a queue of long runs of empty
+// cells).  The queue's count cstart[nc + 1] must be zero before the call (the
+// cell-index kernels clear it) and the queued runs are written by
+// cs_fill_runs in a later kernel (k_gather, or fill_empty_runs).
+size_t cstart_words(uint32_t nc);
 hipError_t cell_starts(const uint32_t* sorted_keys, uint32_t n, uint32_t nc, uint32_t* cstart, hipStream_t st);
+hipError_t fill_empty_runs(uint32_t* cstart, uint32_t nc, hipStream_t st);
 // largest of cstart[c + 1] - cstart[c] over c < nc into *out (statistics)
 hipError_t launch_max_occupancy(const uint32_t* cstart, uint32_t nc, uint32_t* out, hipStream_t st);
 size_t rs_offsets(uint32_t n);

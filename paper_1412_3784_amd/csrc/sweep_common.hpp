@@ -282,6 +282,20 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
   }
 }
 
+// Cell starts: runs of empty cells longer than a span are not filled by
+// the cell-start kernel but queued after cstart[nc] as (first cell, length,
+// value) triples behind a count; a later kernel fills them, each workgroup
+// taking runs blockIdx.x, blockIdx.x + gridDim.x, ...  The count is cleared
+// by the cell-index kernel that precedes the sort.
+__device__ inline void cs_fill_runs(uint32_t* __restrict__ cstart, uint32_t nc) {
+  const uint32_t* runs = cstart + nc + 1;
+  const uint32_t nr = runs[0];
+  for (uint32_t q = blockIdx.x; q < nr; q += gridDim.x) {
+    const uint32_t c0 = runs[1 + 3 * q], len = runs[2 + 3 * q], v = runs[3 + 3 * q];
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) cstart[c0 + i] = v;
+  }
+}
+
 __device__ inline double warp_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

@@ -165,6 +165,24 @@ def test_nonfinite_position_raises_device_flag():
 
 
 @pytest.mark.parametrize("variant", VARS)
+def test_sparse_box_long_empty_runs(variant):
+    """200 WCA particles at density 0.001 (about 10^5 cells, almost all
+    empty): the cell starts of runs of thousands of empty cells are filled by
+    the gather kernel from the queue the cell-start kernel leaves; pair sets,
+    forces and the statistics' largest occupancy must hold."""
+    box = wl.make_box("uniaxial", 0.3, 200, density=0.001, pot=wl.WCA, t_frac=0.3, seed=12)
+    x = oracle_positions(box)
+    x[:20] = x[0] + np.random.default_rng(4).uniform(-0.6, 0.6, size=(20, 3))  # some pairs
+    r = run_oracle(box, x)
+    assert r.stats[1] > 0
+    for prec in ("fp64", "fp32"):
+        g = run_gpu(box, x, variant, prec)
+        compare(g, r, prec, label=f"sparse/{variant}/{prec}")
+        assert g["stats"]["ncells"] > 50000
+        assert 1 <= g["stats"]["max_occupancy"] <= 21
+
+
+@pytest.mark.parametrize("variant", VARS)
 def test_clustered_input_uses_fallback(variant):
     """A dense cluster overflows the LDS tile; those bricks take the
     per-particle path and must still match the oracle."""
