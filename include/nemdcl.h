@@ -57,9 +57,11 @@ extern "C" {
  * FP64:        positions, distances, forces and sums in FP64.
  * FP32:        FP32 offsets of each particle from its FP64 cell centre, FP32
  *              pair maths and per-particle FP32 sums.  Pairs whose r^2 lies
- *              within the rounding band of d_cut^2, and pairs closer than a
- *              close-pair radius, are re-evaluated from FP64 positions exactly
- *              as in FP64 mode, so the interacting set equals the FP64 one.
+ *              within the rounding band of d_cut^2 are re-decided from FP64
+ *              positions exactly as in FP64 mode, so the interacting set
+ *              equals the FP64 one; pairs closer than a close-pair radius
+ *              take their separation and pair terms in FP64 (the force is
+ *              then added to the FP32 sums, the energy to an FP64 sum).
  * FP32_KAHAN:  as FP32, with Kahan-compensated per-particle sums.            */
 #define NCL_PREC_FP64 0
 #define NCL_PREC_FP32 1
