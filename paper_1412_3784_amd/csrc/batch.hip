@@ -235,12 +235,15 @@ __global__ void kb_kick(BatchDev D, double* __restrict__ p, const FT* __restrict
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = D.blk_rep[s / SW_THREADS];
   const uint32_t i = padded_input(D, s, r);
+  // the workgroup's replica's factors exp(-A h / 2), once per workgroup
+  __shared__ double ek[3];
+  if (threadIdx.x < 3) ek[threadIdx.x] = exp(-0.5 * h * D.adiag[3 * (size_t)r + threadIdx.x]);
+  __syncthreads();
   double k2[3] = {0.0, 0.0, 0.0};
   if (i != PAD_SLOT) {
-    const double* a = D.adiag + 3 * (size_t)r;
     for (int d = 0; d < 3; ++d) {
       double v = p[3 * (size_t)i + d];
-      const double e = exp(-0.5 * h * a[d]);
+      const double e = ek[d];
       if (second) {
         v = (v + 0.5 * h * (double)F[3 * (size_t)i + d]) * e;
         k2[d] = v * v / mass;
@@ -266,34 +269,32 @@ __global__ void kb_kick(BatchDev D, double* __restrict__ p, const FT* __restrict
   }
 }
 
+// the workgroup's replica's drift factors exp(A h) and h phi1(A h), phi1(z) =
+// (e^z - 1) / z, once per workgroup (a workgroup never straddles replicas)
+__device__ inline void drift_factors(const BatchDev& D, uint32_t r, double h, double* ez, double* hphi) {
+  if (threadIdx.x < 3) {
+    const double z = D.adiag[3 * (size_t)r + threadIdx.x] * h;
+    ez[threadIdx.x] = exp(z);
+    hphi[threadIdx.x] = h * ((z != 0.0) ? expm1(z) / z : 1.0);
+  }
+  __syncthreads();
+}
+
+// q <- exp(A h) q + h phi1(A h) p / m in the padded input order; wrapping
+// steps then map q back into the reduced box, list steps leave it unwrapped
+// (until the next rebuild)
 __global__ void kb_drift(BatchDev D, double* __restrict__ x, const double* __restrict__ p, double h, double mass,
                          int wrap) {
+  __shared__ double ez[3], hphi[3];
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= D.nslots) return;
-  const uint32_t r = D.blk_rep[s / SW_THREADS];
-  // wrapping steps walk the padded input order; list steps walk the slots,
-  // whose Cartesian copy advances with them
-  const uint32_t i = wrap ? padded_input(D, s, r) : D.perm[s];
+  const uint32_t r = D.blk_rep[blockIdx.x];
+  drift_factors(D, r, h, ez, hphi);
+  const uint32_t i = padded_input(D, s, r);
   if (i == PAD_SLOT) return;
-  const double* a = D.adiag + 3 * (size_t)r;
   double q[3];
-  for (int d = 0; d < 3; ++d) {
-    const double z = a[d] * h;
-    const double phi1 = (z != 0.0) ? expm1(z) / z : 1.0;
-    q[d] = exp(z) * x[3 * (size_t)i + d] + h * phi1 * p[3 * (size_t)i + d] / mass;
-  }
-  if (!wrap) {  // neighbour lists: positions stay unwrapped until the next rebuild
+  for (int d = 0; d < 3; ++d) q[d] = ez[d] * x[3 * (size_t)i + d] + hphi[d] * p[3 * (size_t)i + d] / mass;
+  if (!wrap) {
     for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d];
-    // the slot-ordered copy takes the same affine step
-    const double4 y = D.ysl[s];
-    const double yv[3] = {y.x, y.y, y.z};
-    double yn[3];
-    for (int d = 0; d < 3; ++d) {
-      const double z = a[d] * h;
-      const double phi1 = (z != 0.0) ? expm1(z) / z : 1.0;
-      yn[d] = exp(z) * yv[d] + h * phi1 * p[3 * (size_t)i + d] / mass;
-    }
-    D.ysl[s] = make_double4(yn[0], yn[1], yn[2], 0.0);
     return;
   }
   // back into the reduced box of the new lattice: q - Lred floor(Lred^-1 q)
@@ -303,6 +304,20 @@ __global__ void kb_drift(BatchDev D, double* __restrict__ x, const double* __res
   double n[3];
   for (int d = 0; d < 3; ++d) n[d] = floor(Linv[3 * d] * q[0] + Linv[3 * d + 1] * q[1] + Linv[3 * d + 2] * q[2]);
   for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d] - (L[3 * d] * n[0] + L[3 * d + 1] * n[1] + L[3 * d + 2] * n[2]);
+}
+
+// list steps: the slot-ordered Cartesian copy takes the same affine step
+__global__ void kb_drift_slots(BatchDev D, const double* __restrict__ p, double h, double mass) {
+  __shared__ double ez[3], hphi[3];
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  drift_factors(D, D.blk_rep[blockIdx.x], h, ez, hphi);
+  const uint32_t i = D.perm[s];
+  if (i == PAD_SLOT) return;
+  const double4 y = D.ysl[s];
+  const double yv[3] = {y.x, y.y, y.z};
+  double yn[3];
+  for (int d = 0; d < 3; ++d) yn[d] = ez[d] * yv[d] + hphi[d] * p[3 * (size_t)i + d] / mass;
+  D.ysl[s] = make_double4(yn[0], yn[1], yn[2], 0.0);
 }
 
 // reduced basis of every replica at the prologue's time (for the drift's wrap)
@@ -416,7 +431,8 @@ __global__ void kb_wrap(BatchDev D, double* __restrict__ x) {
 // from the FP64 wrapped positions, both directions of every pair
 template <int VAR>
 __global__ void __launch_bounds__(SW_THREADS) kb_list_build(BatchDev D) {
-  const uint32_t s = blockIdx.x * SW_THREADS + threadIdx.x;
+  // XCD-aware block order: neighbouring slots share an L2
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * SW_THREADS + threadIdx.x;
   if (s >= D.nslots) return;
   const uint32_t r = D.blk_rep[s / SW_THREADS];
   const uint32_t send = D.slot_off[r] + (D.n_off[r + 1] - D.n_off[r]);
@@ -560,7 +576,8 @@ __global__ void kb_mark(BatchDev D, const double* __restrict__ x, int off, doubl
 template <int PREC>
 __global__ void __launch_bounds__(SW_THREADS) kb_list_force(SweepArgs A, BatchDev D, const double* __restrict__ x) {
   __shared__ double shift[27][3];
-  const uint32_t lb = blockIdx.x;
+  // XCD-aware block order: the neighbours of a range of slots stay in one L2
+  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t r = D.blk_rep[lb];
   const CellGeom& g = D.geom[r];
   double L[9];
@@ -658,7 +675,10 @@ hipError_t batch_kick(const BatchDev& D, double* p, const void* F, bool f64, dou
 
 hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st,
                        bool wrap) {
-  if (D.nslots) kb_drift<<<cdivb(D.nslots, 256), 256, 0, st>>>(D, x, p, h, mass, wrap ? 1 : 0);
+  if (D.nslots) {
+    kb_drift<<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D, x, p, h, mass, wrap ? 1 : 0);
+    if (!wrap) kb_drift_slots<<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D, p, h, mass);
+  }
   return hipGetLastError();
 }
 
