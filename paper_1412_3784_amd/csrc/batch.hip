@@ -427,10 +427,21 @@ __global__ void kb_wrap(BatchDev D, double* __restrict__ x) {
   for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d] - (L[3 * d] * n[0] + L[3 * d + 1] * n[1] + L[3 * d + 2] * n[2]);
 }
 
+// group g of slot s's list entries <- this lane's four staged entries
+__device__ inline void store_group(const BatchDev& D, uint32_t s, uint32_t grp, const uint2 (*stage)[SW_THREADS]) {
+  const uint32_t t = threadIdx.x;
+  uint4* dst = reinterpret_cast<uint4*>(D.vl + (((size_t)grp * D.nslots + s) << 2));
+  dst[0] = make_uint4(stage[0][t].x, stage[0][t].y, stage[1][t].x, stage[1][t].y);
+  dst[1] = make_uint4(stage[2][t].x, stage[2][t].y, stage[3][t].x, stage[3][t].y);
+}
+
 // neighbour lists within d_cut + skin (the cut-off the cells were built for),
 // from the FP64 wrapped positions, both directions of every pair
 template <int VAR>
 __global__ void __launch_bounds__(SW_THREADS) kb_list_build(BatchDev D) {
+  // entries are staged per lane in LDS (entry q of the open group of lane t
+  // at stage[q][t]) and stored a whole 32-byte group at a time
+  __shared__ uint2 stage[4][SW_THREADS];
   // XCD-aware block order: neighbouring slots share an L2
   const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * SW_THREADS + threadIdx.x;
   if (s >= D.nslots) return;
@@ -465,13 +476,25 @@ __global__ void __launch_bounds__(SW_THREADS) kb_list_build(BatchDev D) {
       const double xo = pi.x - sx, yo = pi.y - sy, zo = pi.z - sz;
       const bool zero = (m0 | m1 | m2) == 0;
       const uint32_t st = D.cstart[cell0 + c0] + pad, en = D.cstart[cell0 + c1] + pad;
-      for (uint32_t js = st; js < en; ++js) {
-        if (zero && js == s) continue;
-        const double4 pj = D.pos64[js];
-        const double dx = pj.x - xo, dy = pj.y - yo, dz = pj.z - zo;
-        if (fma(dz, dz, fma(dy, dy, dx * dx)) < rl2) {
-          if (cnt < kmax) D.vl[(((size_t)(cnt >> 2) * D.nslots + s) << 2) + (cnt & 3u)] = make_uint2(js, pack_image(m0, m1, m2));
-          ++cnt;
+      const uint32_t self = zero ? s : 0xffffffffu;
+      // four candidate loads in flight per step (indices past the run are
+      // clamped to its last particle and masked out); entries keep the
+      // candidates' order
+      for (uint32_t j0 = st; j0 < en; j0 += 4) {
+        double4 pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = D.pos64[min(j0 + u, en - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t js = j0 + u;
+          const double dx = pj[u].x - xo, dy = pj[u].y - yo, dz = pj[u].z - zo;
+          if (fma(dz, dz, fma(dy, dy, dx * dx)) < rl2 && js < en && js != self) {
+            if (cnt < kmax) {
+              stage[cnt & 3u][threadIdx.x] = make_uint2(js, pack_image(m0, m1, m2));
+              if ((cnt & 3u) == 3u) store_group(D, s, cnt >> 2, stage);
+            }
+            ++cnt;
+          }
         }
       }
     };
@@ -510,6 +533,9 @@ __global__ void __launch_bounds__(SW_THREADS) kb_list_build(BatchDev D) {
         }
       }
     }
+    // the open group (entries past cnt are never read); kmax is a multiple
+    // of four, so an open group exists only below kmax
+    if (cnt < kmax && (cnt & 3u) != 0u) store_group(D, s, cnt >> 2, stage);
     if (cnt > kmax) atomicOr(D.need, 4u);
   }
   D.vl_cnt[s] = cnt < kmax ? cnt : kmax;
