@@ -621,10 +621,18 @@ __global__ void __launch_bounds__(SW_THREADS) kb_list_force(SweepArgs A, BatchDe
       const double4 yi = D.ysl[s];
       const uint32_t n = D.vl_cnt[s];
       const uint4* grp = reinterpret_cast<const uint4*>(D.vl);
+      // the next group's entries are loaded while the current group's
+      // neighbours are evaluated (the last prefetch re-reads group 0)
+      uint4 n01 = make_uint4(0u, 0u, 0u, 0u), n23 = n01;
+      if (n > 0) {
+        n01 = grp[(size_t)s * 2];
+        n23 = grp[(size_t)s * 2 + 1];
+      }
       for (uint32_t k0 = 0; k0 < n; k0 += 4) {
-        // the group: two 16-byte loads, then up to four neighbour loads
-        const size_t gi = ((size_t)(k0 >> 2) * D.nslots + s) * 2;
-        const uint4 e01 = grp[gi], e23 = grp[gi + 1];
+        const uint4 e01 = n01, e23 = n23;
+        const size_t gn = ((size_t)((k0 + 4 < n ? k0 + 4 : 0) >> 2) * D.nslots + s) * 2;
+        n01 = grp[gn];
+        n23 = grp[gn + 1];
         const uint32_t js[4] = {e01.x, e01.z, e23.x, e23.z}, mc[4] = {e01.y, e01.w, e23.y, e23.w};
         double4 yj[4];
 #pragma unroll
