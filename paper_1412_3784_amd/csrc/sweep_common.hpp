@@ -58,8 +58,9 @@ __device__ inline uint64_t splitmix_out(uint64_t z) {
 
 template <int PREC, bool DEBUG>
 struct Acc {
-  // FP32 modes: per-particle FP32 sums (+ Kahan terms), FP64 sums for the
-  // pairs taken on the FP64 path.  FP64 mode uses only the double fields.
+  // FP32 modes: per-particle FP32 sums (+ Kahan terms); the energy of the
+  // pairs taken on the FP64 path goes to gu (the half list also keeps their
+  // forces in gx, gy, gz).  FP64 mode uses only the double fields.
   float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f;
   float kx = 0.f, ky = 0.f, kz = 0.f, ku = 0.f;
   float w[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -190,7 +191,7 @@ __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, Pai
 
 // Visit one neighbour cell `cj` seen through lattice image `m` (in the
 // basis Lred); `dc` is the FP64 vector from the home cell's centre to the
-// centre of that image of cj, `sh` the lattice shift B m in the frame.
+// centre of that image of cj (the FP64 paths form the shift B m from m).
 //
 // FLAT: the slots [cstart[cj], cstart[cj + ncell]) of ncell consecutive x
 // cells of one row (cells are stored x-fastest), for the rectangular cells
