@@ -237,16 +237,18 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
     // end) are read and masked out
     // dynamic size: the self-exclusion test is compiled in only for the
     // visits (wave-wide) that hold some lane's own particle (measured 3 %
-    // faster; the dynamic-offset runs keep the test, where the second copy
-    // of the loop cost registers and time)
+    // faster).  The dynamic-offset runs take the plain copy of the loop
+    // below, with the test: a second copy cost them registers and time, and
+    // routing them through this lambda changed their code (the batched sweep
+    // ran 2-3 % slower).
     auto run = [&](auto check_self) {
       constexpr bool CHECK_SELF = decltype(check_self)::value;
       const float4* pp = A.pos32 + st;
       for (uint32_t j0 = st; j0 < en; j0 += 4, pp += 4) {
         float4 pj[4];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < 4; ++u) pj[u] = pp[u];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t j = j0 + u;
           double dx = (double)pj[u].x - xo;
@@ -288,11 +290,56 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
         if (__ballot(L.q > L.base + (PL_K - 4) * PL_STRIDE) != 0) flush_list(acc, A, L);
       }
     };
-    if constexpr (FLAT) {
-      run(std::true_type{});
-    } else {
+    if constexpr (!FLAT) {
       if (__ballot(self >= st && self < en) != 0) run(std::true_type{});
       else run(std::false_type{});
+    } else {
+      const float4* pp = A.pos32 + st;
+      for (uint32_t j0 = st; j0 < en; j0 += 4, pp += 4) {
+        float4 pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = pp[u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t j = j0 + u;
+          double dx = (double)pj[u].x - xo;
+          if (FLAT) dx = fma((double)(int32_t)(__float_as_uint(pj[u].w) - rowbase), g.w[0], dx);
+          const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          if (r2 < g.rc2_hi64 && j < en && j != self) {
+            if (DEBUG || r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
+              // within the rounding band of d_cut, or a close pair: re-evaluate
+              // from the FP64 positions exactly as the FP64 mode does
+              const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
+              const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
+              const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
+              // the home position is re-read here rather than kept in
+              // registers through the loop (this path is rare)
+              const double4 ph64 = A.pos64[s];
+              const double xo64 = ph64.x - sx, yo64 = ph64.y - sy, zo64 = ph64.z - sz;
+              const double4 pj64 = A.pos64[j];
+              const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
+              const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+              acc.fp64 += 1;
+              if (e2 < A.rc2) {
+                if (e2 < A.rclose2_64)
+                  pair64(acc, A.p64, ex, ey, ez, e2);
+                else
+                  pair32(acc, A.p32, (float)ex, (float)ey, (float)ez, (float)e2);
+                acc.pairs += 1;
+                debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
+              }
+            } else {
+              L.q[0] = (float)dx;
+              L.q[1] = (float)dy;
+              L.q[2] = (float)dz;
+              L.q += PL_STRIDE;
+            }
+          }
+        }
+        // the next group appends at most four entries per lane
+        if (__ballot(L.q > L.base + (PL_K - 4) * PL_STRIDE) != 0) flush_list(acc, A, L);
+      }
     }
   }
 }
