@@ -532,7 +532,7 @@ static uint64_t tune_key(const ncl_ctx* h) {
   return k | ((uint64_t)(h->deterministic & 1) << 60);
 }
 
-static hipError_t sweep_with(ncl_ctx* h, SweepArgs* A, int mode, const int* brick, void* F, double* U, double* W) {
+static hipError_t sweep_with(ncl_ctx* h, SweepArgs* A, int mode, const int* brick, double* U, double* W) {
   for (int k = 0; k < 6; ++k) h->brick[k] = brick[k];
   brick_args(h, A);
   SweepLaunch L;
@@ -556,7 +556,7 @@ static bool half_ok(const ncl_ctx* h) {
 // one untimed launch) with HIP events; the fastest is cached for the class.
 // The half list is a candidate only when run-to-run identical forces are not
 // required.
-static int autotune(ncl_ctx* h, SweepArgs* A, void* F, double* U, double* W, ncl_ctx::Tuned* out) {
+static int autotune(ncl_ctx* h, SweepArgs* A, double* U, double* W, ncl_ctx::Tuned* out) {
   int modes[5], bricks[5][6], nc = 0;
   modes[nc] = SWEEP_PARTICLE;
   for (int k = 0; k < 6; ++k) bricks[nc][k] = h->cand[0][k];
@@ -578,9 +578,9 @@ static int autotune(ncl_ctx* h, SweepArgs* A, void* F, double* U, double* W, ncl
   out->key = tune_key(h);
   for (int c = 0; c < 5; ++c) out->ms[c] = -1.0f;
   for (int c = 0; c < nc; ++c) {
-    hipError_t e = sweep_with(h, A, modes[c], bricks[c], F, U, W);
+    hipError_t e = sweep_with(h, A, modes[c], bricks[c], U, W);
     if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-    if (e == hipSuccess) e = sweep_with(h, A, modes[c], bricks[c], F, U, W);
+    if (e == hipSuccess) e = sweep_with(h, A, modes[c], bricks[c], U, W);
     if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.0f;
@@ -622,7 +622,7 @@ int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
       if (e.key == key) t = &e;
     if (!t) {
       ncl_ctx::Tuned nt{};
-      const int rc = autotune(h, &A, F, U, W, &nt);
+      const int rc = autotune(h, &A, U, W, &nt);
       if (rc) return rc;
       h->tuned.push_back(nt);
       t = &h->tuned.back();
@@ -631,7 +631,7 @@ int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
     mode = t->mode;
     for (int k = 0; k < 6; ++k) brick[k] = t->brick[k];
   }
-  hipError_t e = sweep_with(h, &A, mode, brick, F, U, W);
+  hipError_t e = sweep_with(h, &A, mode, brick, U, W);
   if (e != hipSuccess) return hip_fail(h, e, "sweep launch");
   h->used_mode = mode;
   for (int k = 0; k < 3; ++k) h->used_brick[k] = mode == SWEEP_TILED ? brick[k] : 0;

@@ -493,7 +493,7 @@ static int sllod_run_lists(ncl_batch* b, const BatchDev& D, const SweepArgs& A, 
   };
   if (e == hipSuccess) e = batch_prologue(D, 0, h, st);
   if (e == hipSuccess) code = rebuild(0);
-  if (e == hipSuccess && code == NCL_OK) e = batch_list_force(A, D, x, b->precision, U, W, st);
+  if (e == hipSuccess && code == NCL_OK) e = batch_list_force(A, D, b->precision, U, W, st);
   if (e == hipSuccess && code == NCL_OK) e = batch_kick(D, p, F, f64, 0.0, mass, 1, st);
   if (e == hipSuccess && code == NCL_OK) e = batch_observe(D, U, W, h, hist, hist_cap, false, st);
   for (int64_t k = 0; k < nsteps && e == hipSuccess && code == NCL_OK; ++k) {
@@ -504,7 +504,7 @@ static int sllod_run_lists(ncl_batch* b, const BatchDev& D, const SweepArgs& A, 
     if ((e = batch_list_check(D, x, 1, h, b->skin, st)) != hipSuccess) break;
     if ((e = read_need(&need)) != hipSuccess) break;
     if (need && (code = rebuild(1)) != NCL_OK) break;
-    if ((e = batch_list_force(A, D, x, b->precision, U, W, st)) != hipSuccess) break;
+    if ((e = batch_list_force(A, D, b->precision, U, W, st)) != hipSuccess) break;
     if ((e = batch_kick(D, p, F, f64, h, mass, 1, st)) != hipSuccess) break;
     e = batch_observe(D, U, W, h, hist, hist_cap, true, st);
   }

@@ -600,7 +600,7 @@ __global__ void kb_mark(BatchDev D, const double* __restrict__ x, int off, doubl
 // taken four at a time (their neighbour loads issued together), and the 27
 // lattice shifts L m with m in {-1,0,1}^3 come from LDS.
 template <int PREC>
-__global__ void __launch_bounds__(SW_THREADS) kb_list_force(SweepArgs A, BatchDev D, const double* __restrict__ x) {
+__global__ void __launch_bounds__(SW_THREADS) kb_list_force(SweepArgs A, BatchDev D) {
   __shared__ double shift[27][3];
   // XCD-aware block order: the neighbours of a range of slots stay in one L2
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -751,13 +751,13 @@ hipError_t batch_list_check(const BatchDev& D, const double* x, int off, double 
   return hipGetLastError();
 }
 
-hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, const double* x, int precision, double* U,
-                            double* W, hipStream_t st) {
+hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, int precision, double* U, double* W,
+                            hipStream_t st) {
   kb_fill_u32<<<1, 64, 0, st>>>((uint32_t*)A.stats, 8, 0u);
   if (D.nslots) {
-    if (precision == 0) kb_list_force<0><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D, x);
-    else if (precision == 2) kb_list_force<2><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D, x);
-    else kb_list_force<1><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D, x);
+    if (precision == 0) kb_list_force<0><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
+    else if (precision == 2) kb_list_force<2><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
+    else kb_list_force<1><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
   }
   kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 1);
   return hipGetLastError();

@@ -55,8 +55,8 @@ hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, 
 hipError_t batch_wrap(const BatchDev& D, double* x, hipStream_t st);
 hipError_t batch_list_rebuild(const BatchDev& D, double* x, int off, double h, hipStream_t st);
 hipError_t batch_list_check(const BatchDev& D, const double* x, int off, double h, double skin, hipStream_t st);
-hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, const double* x, int precision, double* U,
-                            double* W, hipStream_t st);
+hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, int precision, double* U, double* W,
+                            hipStream_t st);
 hipError_t batch_observe(const BatchDev& D, const double* U, const double* W, double h, double* hist,
                          uint32_t hist_cap, bool advance, hipStream_t st);
 
