@@ -33,8 +33,8 @@
 
 namespace ncl {
 
-constexpr int HL_K = 8;        // per-lane list of pairs waiting for evaluation
-constexpr int HW_CAP = 2000;   // window accumulators per workgroup (particles)
+constexpr int HL_K = 7;        // per-lane list of pairs waiting for evaluation
+constexpr int HW_CAP = 1984;   // window accumulators per workgroup (particles; two workgroups per CU)
 constexpr int HW_ROWS = 4;     // home rows per workgroup that get windows
 constexpr int HW_WPR = 6;      // windows per home row
 constexpr int HW_SEGS = 64;    // segments over all windows of a workgroup
@@ -42,7 +42,7 @@ constexpr int NO_WIN = INT32_MIN;  // run without a window (a real base may be n
 
 struct HalfSmem {
   unsigned long long fx[HW_CAP], fy[HW_CAP], fz[HW_CAP];  // fixed point, units of q
-  float list[HL_K * SW_THREADS * 3];
+  pl_entry list[HL_K * SW_THREADS];  // (d_x, d_y, d_z, r^2) as in the full sweep's list
   uint16_t tgt[HL_K * SW_THREADS];
   int32_t seg_off[HW_SEGS + 1];        // first accumulator of each segment
   int32_t seg_base[HW_SEGS];           // accumulator of slot j = j + seg_base
@@ -54,7 +54,7 @@ struct HalfSmem {
 };
 
 struct HList {
-  float* base;
+  pl_entry* base;
   uint16_t* tgt;
   int cnt;
 };
@@ -269,10 +269,10 @@ __device__ inline unsigned long long to_fix(float v, double inv_q) {
 template <bool DEBUG>
 __device__ inline void hflush(Acc<1, DEBUG>& acc, const SweepArgs& A, HalfSmem& S, HList& L) {
   for (int e = 0; e < L.cnt; ++e) {
-    const float* q = L.base + e * (SW_THREADS * 3);
-    const float dx = q[0], dy = q[1], dz = q[2];
+    const pl_entry q = L.base[e * SW_THREADS];
+    const float dx = q.x, dy = q.y, dz = q.z;
     const int t = L.tgt[e * SW_THREADS];
-    const float fs = hpair32(acc, A.p32, dx, dy, dz, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    const float fs = hpair32(acc, A.p32, dx, dy, dz, q.w);
     atomicAdd(&S.fx[t], to_fix(fs * dx, A.fix_inv));
     atomicAdd(&S.fy[t], to_fix(fs * dy, A.fix_inv));
     atomicAdd(&S.fz[t], to_fix(fs * dz, A.fix_inv));
@@ -346,7 +346,7 @@ __device__ inline void hvisit(Acc<1, DEBUG>& acc, const SweepArgs& A, const Cell
             }
           } else {
             const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-            const float fs = hpair32(acc, A.p32, fx, fy, fz, fmaf(fz, fz, fmaf(fy, fy, fx * fx)));
+            const float fs = hpair32(acc, A.p32, fx, fy, fz, (float)r2);
             fj[0] = (double)(fs * fx); fj[1] = (double)(fs * fy); fj[2] = (double)(fs * fz);
           }
           if (hit) {
@@ -354,10 +354,7 @@ __device__ inline void hvisit(Acc<1, DEBUG>& acc, const SweepArgs& A, const Cell
             acc.pairs += 2;
           }
         } else {
-          float* q = L.base + L.cnt * (SW_THREADS * 3);
-          q[0] = (float)dx;
-          q[1] = (float)dy;
-          q[2] = (float)dz;
+          L.base[L.cnt * SW_THREADS] = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
           L.tgt[L.cnt * SW_THREADS] = (uint16_t)(rb + (int)j);
           L.cnt += 1;
           acc.pairs += 2;
@@ -443,7 +440,7 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_half(SweepArgs A, CellGeom
   Acc<1, DEBUG> acc;
   uint32_t nbh = 0;
   if (s < s1) {
-    HList L{S.list + 3 * threadIdx.x, S.tgt + threadIdx.x, 0};
+    HList L{S.list + threadIdx.x, S.tgt + threadIdx.x, 0};
     sweep_half<VAR, DEBUG>(A, g, S, s, acc, nbh, L, Facc);
     hflush(acc, A, S, L);
     add_f64(Facc, s, (double)acc.fx + acc.gx, (double)acc.fy + acc.gy, (double)acc.fz + acc.gz);

@@ -451,7 +451,7 @@ overflow:
 // particle from global memory
 template <int VAR, int PREC, bool DEBUG>
 __global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, CellGeom g) {
-  __shared__ float plist[PL_K * SW_THREADS_P * 3];
+  __shared__ pl_entry plist[PL_K * SW_THREADS_P];
   const uint32_t nover = A.overflow[0];
   const int l0 = g.nc[0], l1 = g.nc[1], l2 = g.nc[2];
   for (uint32_t q = blockIdx.x; q < nover; q += gridDim.x) {
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, Cell
         for (uint32_t s = s0 + threadIdx.x; s < s1; s += SW_THREADS) {
           Acc<PREC, DEBUG> acc;
           uint32_t nbh = 0;
-          PairList L(plist + 3 * threadIdx.x);
+          PairList L(plist + threadIdx.x);
           sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
           write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
           double v[7];
@@ -493,13 +493,13 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, Cell
 // measured 0.80 -> 0.70 ms at 1 M LJ.
 template <int VAR, int PREC, bool DEBUG>
 __global__ void __launch_bounds__(SW_THREADS, 4) k_sweep_particle(SweepArgs A, CellGeom g) {
-  __shared__ float plist[PL_K * SW_THREADS_P * 3];
+  __shared__ pl_entry plist[PL_K * SW_THREADS_P];
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t s = lb * SW_THREADS + threadIdx.x;
   Acc<PREC, DEBUG> acc;
   uint32_t nbh = 0;
   if (s < A.n) {
-    PairList L(plist + 3 * threadIdx.x);
+    PairList L(plist + threadIdx.x);
     sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
   }

@@ -165,25 +165,30 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
   cnt += 1;
 }
 
-// Per-lane list of in-range separations waiting for evaluation (LDS,
-// entry e of lane t at base[(e * SW_THREADS + t) * 3]); evaluated by whole
-// waves so that no lane runs the pair code alone.  `q` is the lane's next
+// Per-lane list of in-range pairs waiting for evaluation (LDS, entry e of
+// lane t at base[e * SW_THREADS + t]); evaluated by whole waves so that no
+// lane runs the pair code alone.  An entry holds the separation in FP32 and
+// r^2 rounded once from the FP64 screening value: recomputing r^2 from the
+// three rounded components instead would add their rounding, which the WCA
+// force near its cut-off (|f'| about 75 eps/sigma^2 at r = 1.11 sigma)
+// magnifies to ~1e-5 eps/sigma for an isolated pair.  `q` is the lane's next
 // free entry; the pairs are counted when the list is evaluated.
-constexpr int PL_K = 13;
+constexpr int PL_K = 9;
 constexpr int SW_THREADS_P = 256;
-constexpr int PL_STRIDE = SW_THREADS_P * 3;
-typedef __attribute__((address_space(3))) float lds_float;  // 32-bit LDS pointer
+constexpr int PL_STRIDE = SW_THREADS_P;  // in entries
+typedef float pl_entry __attribute__((ext_vector_type(4)));      // (d_x, d_y, d_z, r^2)
+typedef __attribute__((address_space(3))) pl_entry lds_entry;  // 32-bit LDS pointer
 struct PairList {
-  lds_float* base;
-  lds_float* q;
-  __device__ explicit PairList(float* p) : base((lds_float*)p), q((lds_float*)p) {}
+  lds_entry* base;
+  lds_entry* q;
+  __device__ explicit PairList(pl_entry* p) : base((lds_entry*)p), q((lds_entry*)p) {}
 };
 
 template <int PREC, bool DEBUG>
 __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PairList& L) {
-  for (const lds_float* e = L.base; e != L.q; e += PL_STRIDE) {
-    const float dx = e[0], dy = e[1], dz = e[2];
-    pair32(acc, A.p32, dx, dy, dz, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  for (const lds_entry* e = L.base; e != L.q; e += PL_STRIDE) {
+    const pl_entry v = *e;
+    pair32(acc, A.p32, v.x, v.y, v.z, v.w);
     acc.pairs += 1;
   }
   L.q = L.base;
@@ -279,9 +284,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                 debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
               }
             } else {
-              L.q[0] = (float)dx;
-              L.q[1] = (float)dy;
-              L.q[2] = (float)dz;
+              *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
               L.q += PL_STRIDE;
             }
           }
@@ -330,9 +333,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                 debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
               }
             } else {
-              L.q[0] = (float)dx;
-              L.q[1] = (float)dy;
-              L.q[2] = (float)dz;
+              *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
               L.q += PL_STRIDE;
             }
           }
