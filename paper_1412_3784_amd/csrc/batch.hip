@@ -139,7 +139,7 @@ __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
 // one thread per slot; the workgroup's replica fixes the geometry
 template <int VAR, int PREC, bool DEBUG>
 __global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev D) {  // four waves per SIMD
-  __shared__ pl_entry plist[PL_K * SW_THREADS_P];
+  __shared__ SweepSmem sm;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t r = D.blk_rep[lb];
   const CellGeom& g = D.geom[r];
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev
   const bool skip = g.variant < 0 || (D.err[0] & 1) != 0;
   if (s < send) {
     if (!skip) {
-      PairList L(plist + threadIdx.x);
+      PairList L(sm.plist + threadIdx.x);
       sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
     }
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev
   double v[7];
   acc_energy(acc, v);
   const uint32_t st4[4] = {acc.cand, acc.pairs, acc.fp64, nbh};
-  block_commit(A, lb, v, st4);
+  block_commit(A, lb, v, st4, sm.red);
 }
 
 // per replica: U = 1/2 sum u, W = 1/2 sum w over its workgroups, in order;

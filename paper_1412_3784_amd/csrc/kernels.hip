@@ -488,25 +488,26 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, Cell
 
 // one thread per particle in cell order, neighbour data straight from
 // global memory (L1/L2); partial sums per workgroup.  Four waves per SIMD
-// (at most 128 VGPRs; the 13-deep pair list keeps the LDS of four
-// workgroups per CU within 160 KB) hide more load latency than three:
-// measured 0.80 -> 0.70 ms at 1 M LJ.
+// (at most 128 VGPRs; the 10-deep list of 16-byte entries, whose LDS the
+// block's reduction reuses, makes 40 KB, so four workgroups fill the CU's
+// 160 KB) hide more load latency than three: measured 0.80 -> 0.70 ms at
+// 1 M LJ.
 template <int VAR, int PREC, bool DEBUG>
 __global__ void __launch_bounds__(SW_THREADS, 4) k_sweep_particle(SweepArgs A, CellGeom g) {
-  __shared__ pl_entry plist[PL_K * SW_THREADS_P];
+  __shared__ SweepSmem sm;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t s = lb * SW_THREADS + threadIdx.x;
   Acc<PREC, DEBUG> acc;
   uint32_t nbh = 0;
   if (s < A.n) {
-    PairList L(plist + threadIdx.x);
+    PairList L(sm.plist + threadIdx.x);
     sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
   }
   double v[7];
   acc_energy(acc, v);
   const uint32_t st4[4] = {acc.cand, acc.pairs, acc.fp64, nbh};
-  block_commit(A, lb, v, st4);
+  block_commit(A, lb, v, st4, sm.red);
 }
 
 // first level of the fixed-order reduction: block r sums partial slots

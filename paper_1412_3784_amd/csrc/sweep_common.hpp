@@ -173,7 +173,7 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 // force near its cut-off (|f'| about 75 eps/sigma^2 at r = 1.11 sigma)
 // magnifies to ~1e-5 eps/sigma for an isolated pair.  `q` is the lane's next
 // free entry; the pairs are counted when the list is evaluated.
-constexpr int PL_K = 9;
+constexpr int PL_K = 10;
 constexpr int SW_THREADS_P = 256;
 constexpr int PL_STRIDE = SW_THREADS_P;  // in entries
 typedef float pl_entry __attribute__((ext_vector_type(4)));      // (d_x, d_y, d_z, r^2)
@@ -494,9 +494,11 @@ __device__ inline void acc_energy(const Acc<PREC, DEBUG>& acc, double* v) {
 // -> partial[PART_STRIDE * slot], summed over slots by the finalisation.
 // (Statistics are not added atomically: one counter hit by every wave of a
 // launch serialises in one L2 channel and cost a quarter of the sweep.)
-// Every thread of the block must call it.
-__device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const double* v, const uint32_t* st4) {
-  __shared__ double red[4][PART_STRIDE];
+// Every thread of the block must call it.  `red` is LDS for the four
+// waves' sums; it may alias memory the block has finished with (the pair
+// lists), since the block synchronises before writing it.
+__device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const double* v, const uint32_t* st4,
+                                    double (*red)[PART_STRIDE]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
 #pragma unroll
@@ -517,6 +519,18 @@ __device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const dou
     A.partial[PART_STRIDE * (size_t)slot + threadIdx.x] = t;
   }
 }
+
+__device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const double* v, const uint32_t* st4) {
+  __shared__ double red[4][PART_STRIDE];
+  block_commit(A, slot, v, st4, red);
+}
+
+// LDS of the per-particle sweeps: the per-lane pair lists, reused for the
+// block's reduction once every lane has flushed its list
+union SweepSmem {
+  pl_entry plist[PL_K * SW_THREADS_P];
+  double red[4][PART_STRIDE];
+};
 
 
 }  // namespace ncl
