@@ -5,9 +5,10 @@ LJ, cell-list variant, precision and sweep schedule (LDS-tiled, per
 particle, autotuned, or the half list in FP32) are drawn per case, and the
 pair sets, forces, energy and virial are compared with the FP64 oracle.
 The cell counts of these boxes (6- to 18-bit keys) take one radix pass of a
-6- to 10-bit digit or two passes of up to 9 bits.  Each case runs the debug
-build (pair sets) and the production build (forces through the per-lane
-pair lists)."""
+6- to 10-bit digit or two passes of up to 9 bits.  Each case is built
+twice: with pair digests (debug = 1; the pair sets come from the digest
+sweep) and without; both times forces, energy and virial come from the
+production sweep."""
 import numpy as np
 import pytest
 
@@ -57,12 +58,12 @@ def test_random_box(seed):
     x = oracle_positions(box)
     r = run_oracle(box, x)
     label = f"seed{seed}/{box.flow}/n{len(x)}/{variant}/{precision}/sweep{sweep}"
-    # debug build: pair sets (count and digest per particle) and forces
+    # built with pair digests: pair sets (count and digest per particle),
+    # forces from the production sweep
     g = run_gpu(box, x, variant, precision, options={SWEEP_OPT: sweep})
     compare(g, r, precision, label=label)
     assert g["stats"]["pairs"] == r.stats[1], label
-    # production build (in-range pairs through the per-lane lists): forces,
-    # energy, virial and the pair count
+    # built without digests: forces, energy, virial and the pair count
     g = run_gpu(box, x, variant, precision, debug=False, options={SWEEP_OPT: sweep})
     compare(g, r, precision, check_pairs=False, label=label + "/nodebug")
     assert g["stats"]["pairs"] == r.stats[1], label
