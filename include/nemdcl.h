@@ -56,7 +56,10 @@ extern "C" {
 /* arithmetic of the pair sweep.
  * FP64:        positions, distances, forces and sums in FP64.
  * FP32:        FP32 offsets of each particle from its FP64 cell centre, FP32
- *              pair maths and per-particle FP32 sums.  Pairs whose r^2 lies
+ *              pair maths and per-particle FP32 sums; the pair maths take
+ *              r^2 rounded once from the FP64 screen of the separation (not
+ *              recomputed from its FP32 components, whose rounding the WCA
+ *              force near d_cut would magnify).  Pairs whose r^2 lies
  *              within the rounding band of d_cut^2 are re-decided from FP64
  *              positions exactly as in FP64 mode, so the interacting set
  *              equals the FP64 one; pairs closer than a close-pair radius
