@@ -361,7 +361,7 @@ __device__ inline void hvisit(Acc<1, DEBUG>& acc, const SweepArgs& A, const Cell
         }
       }
     }
-    if (__ballot(L.cnt > HL_K - 5) != 0) hflush(acc, A, S, L);
+    if (__ballot(L.cnt > HL_K - 4) != 0) hflush(acc, A, S, L);  // a group appends at most four
   }
 }
 
