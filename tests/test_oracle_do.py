@@ -92,3 +92,21 @@ def test_aligned_layers_need_no_expansion(orc):
     tot = sum(len(orc.do_neighbourhood(R, l, 1.0, a, b, c, tight=False))
               for a in range(l[0]) for b in range(l[1]) for c in range(l[2]))
     assert abs(tot / np.prod(l) - (27 + 6 / l[1])) < 1e-12
+
+
+def test_two_dimensional_top_row_count(orc):
+    """Sec. 4.2, 2-D discussion: a cell in the top row of a rectangular box
+    whose top neighbours are shifted by the face offset needs ten cells (the
+    crossing row overlaps four cells).  With r13 = r23 = 0 every z layer is
+    this 2-D case: the home layer of a top-row cell holds ten (cell, image)
+    entries, an interior row's nine."""
+    gold = read_golden()
+    l = [6, 5, 7]
+    R = generic_R(l, 1.0, 4)
+    R[0, 2] = R[1, 2] = 0.0
+    c = 3
+    for a in range(l[0]):
+        for b, expect in ((l[1] - 1, gold["do_2d_top_row_cells"]), (0, gold["do_2d_top_row_cells"]), (2, 9)):
+            nb = orc.do_neighbourhood(R, l, 1.0, a, b, c)
+            layer = nb[(nb[:, 2] == c) & (nb[:, 5] == 0)]
+            assert len(layer) == expect, (a, b, len(layer))

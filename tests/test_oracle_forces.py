@@ -81,6 +81,35 @@ def test_cells_equal_brute(orc, flow, side, tf, seed):
     assert np.abs(b.W - c.W).max() <= 1e-12 * (np.abs(b.W).max() + 1)
 
 
+MEDIUM = [(flow, pot_name, tf) for flow in ("planar", "uniaxial", "biaxial", "shear", "none")
+          for pot_name, tf in (("wca", 0.4), ("lj", 0.5))]
+
+
+@pytest.mark.parametrize("flow,pot_name,tf", MEDIUM)
+def test_cells_equal_brute_medium(orc, flow, pot_name, tf):
+    """Sec. 4.1 cell list == brute force on medium boxes (at least 5 cells per
+    side: 1,500 WCA or 6,000 LJ particles at liquid density), every flow:
+    pair sets, forces, energy and virial."""
+    if pot_name == "wca":
+        pot, n, dens = WCA, 1500, 0.8442
+    else:
+        pot, n, dens = wl.LJ25, 6000, 0.8
+    box = wl.make_box(flow, 0.5, n, density=dens, pot=pot, t_frac=tf, seed=211)
+    Lt = orc.lattice_at(box.L0, box.A, box.t)
+    Lred, Mtot, _ = orc.reduce(box.L0, box.A, box.t, box.automorphisms)
+    assert orc.ds_counts(Lred, pot.rc).min() >= 5
+    x = box.positions(Lt)
+    b = orc.forces_brute(x, Lred, pot, Mkey=Mtot)
+    c = orc.forces_cells(x, Lred, pot, Mkey=Mtot)
+    assert b.count.sum() > 2 * n
+    assert (b.count == c.count).all()
+    assert (b.hash == c.hash).all()
+    scale = np.abs(b.F).max() + 1.0
+    assert np.abs(b.F - c.F).max() <= 1e-12 * scale
+    assert abs(b.U - c.U) <= 1e-12 * (abs(b.U) + 1)
+    assert np.abs(b.W - c.W).max() <= 1e-12 * (np.abs(b.W).max() + 1)
+
+
 def jittered_lattice(n_side, L, sigma, seed):
     g = np.random.default_rng(seed)
     ax = (np.arange(n_side) + 0.5) / n_side
