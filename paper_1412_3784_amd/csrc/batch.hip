@@ -660,7 +660,7 @@ __global__ void __launch_bounds__(SW_THREADS) kb_list_force(SweepArgs A, BatchDe
             if (PREC == 0 || r2 < A.rclose2_64)
               pair64(acc, A.p64, dx, dy, dz, r2);
             else
-              pair32(acc, A.p32, (float)dx, (float)dy, (float)dz, (float)r2);
+              pair32(acc, A.p32, A.p64, (float)dx, (float)dy, (float)dz, (float)r2, r2);
             acc.pairs += 1;
           }
         }

@@ -209,16 +209,16 @@ __device__ inline int run_base(const HalfSmem& S, int hrow, int wl, int i, uint3
 // one FP32 pair: accumulates the home particle's force, energy and virial
 // and returns fs, the neighbour's force being fs * d (d = x_j - x_i)
 template <bool DEBUG>
-__device__ inline float hpair32(Acc<1, DEBUG>& acc, const Pot32& p, float dx, float dy, float dz, float r2) {
+__device__ inline float hpair32(Acc<1, DEBUG>& acc, const Pot32& p, const Pot64& p64, float dx, float dy, float dz,
+                               float r2, double r2e) {
   const float r2i = __builtin_amdgcn_rcpf(r2);
   const float s2 = p.sig2 * r2i;
   const float s6 = s2 * s2 * s2;
   const float fs = r2i * s6 * fmaf(p.eps48, s6, -p.eps24);
-  const float phi = fmaf(s6, fmaf(p.eps4, s6, -p.eps4), -p.shift);
   acc.fx = fmaf(-fs, dx, acc.fx);
   acc.fy = fmaf(-fs, dy, acc.fy);
   acc.fz = fmaf(-fs, dz, acc.fz);
-  acc.u += phi;
+  acc.gu += phi64(p64, r2e, r2i);  // energy in FP64, as in the full list
   const float fdx = fs * dx, fdy = fs * dy;
   acc.w[0] = fmaf(fdx, dx, acc.w[0]);
   acc.w[1] = fmaf(fdy, dy, acc.w[1]);
@@ -272,7 +272,7 @@ __device__ inline void hflush(Acc<1, DEBUG>& acc, const SweepArgs& A, HalfSmem& 
     const pl_entry q = L.base[e * SW_THREADS];
     const float dx = q.x, dy = q.y, dz = q.z;
     const int t = L.tgt[e * SW_THREADS];
-    const float fs = hpair32(acc, A.p32, dx, dy, dz, q.w);
+    const float fs = hpair32(acc, A.p32, A.p64, dx, dy, dz, q.w, (double)q.w);
     atomicAdd(&S.fx[t], to_fix(fs * dx, A.fix_inv));
     atomicAdd(&S.fy[t], to_fix(fs * dy, A.fix_inv));
     atomicAdd(&S.fz[t], to_fix(fs * dz, A.fix_inv));
@@ -306,7 +306,7 @@ __device__ inline void hvisit(Acc<1, DEBUG>& acc, const SweepArgs& A, const Cell
       const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
       const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
       if (r2 < g.rc2_hi64 && j < en) {
-        const bool exact = DEBUG || r2 > g.rc2_lo64 || r2 < A.rclose2_64;
+        const bool exact = r2 > g.rc2_lo64 || r2 < A.rclose2_64;
         if (exact || rb == NO_WIN || r2 < A.rwin2_64) {
           double fj[3];
           bool hit = true;
@@ -339,15 +339,16 @@ __device__ inline void hvisit(Acc<1, DEBUG>& acc, const SweepArgs& A, const Cell
                 fj[0] = fs * ex; fj[1] = fs * ey; fj[2] = fs * ez;
               } else {
                 const float fx = (float)ex, fy = (float)ey, fz = (float)ez;
-                const float fs = hpair32(acc, A.p32, fx, fy, fz, (float)e2);
+                const float fs = hpair32(acc, A.p32, A.p64, fx, fy, fz, (float)e2, e2);
                 fj[0] = (double)(fs * fx); fj[1] = (double)(fs * fy); fj[2] = (double)(fs * fz);
               }
               debug_both<DEBUG>(acc, A, g, s, j, m, wi);
             }
           } else {
             const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-            const float fs = hpair32(acc, A.p32, fx, fy, fz, (float)r2);
+            const float fs = hpair32(acc, A.p32, A.p64, fx, fy, fz, (float)r2, r2);
             fj[0] = (double)(fs * fx); fj[1] = (double)(fs * fy); fj[2] = (double)(fs * fz);
+            debug_both<DEBUG>(acc, A, g, s, j, m, wi);
           }
           if (hit) {
             add_f64(Facc, j, fj[0], fj[1], fj[2]);
@@ -358,6 +359,7 @@ __device__ inline void hvisit(Acc<1, DEBUG>& acc, const SweepArgs& A, const Cell
           L.tgt[L.cnt * SW_THREADS] = (uint16_t)(rb + (int)j);
           L.cnt += 1;
           acc.pairs += 2;
+          debug_both<DEBUG>(acc, A, g, s, j, m, wi);
         }
       }
     }

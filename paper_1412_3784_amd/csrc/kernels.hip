@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_tile(SweepArgs A, CellGeom
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           const bool band = fabs(r2 - A.rc2) <= A.band64;
           const bool close = r2 < A.rclose2_64;
-          if (PREC == 0 || DEBUG || band || close) {
+          if (PREC == 0 || band || close) {
             // exact path: recover the lattice image and re-form the
             // separation from FP64 wrapped positions
             const uint32_t gj = __float_as_uint(q.w);
@@ -352,13 +352,24 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_tile(SweepArgs A, CellGeom
               if (PREC == 0 || close)
                 pair64(acc, A.p64, ex, ey, ez, e2);
               else
-                pair32(acc, A.p32, (float)ex, (float)ey, (float)ez, (float)e2);
+                pair32(acc, A.p32, A.p64, (float)ex, (float)ey, (float)ez, (float)e2, e2);
               acc.pairs += 1;
               debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, gj, m, wi);
             }
           } else if (r2 < A.rc2) {
-            pair32(acc, A.p32, (float)dx, (float)dy, (float)dz, (float)r2);
+            pair32(acc, A.p32, A.p64, (float)dx, (float)dy, (float)dz, (float)r2, r2);
             acc.pairs += 1;
+            if (DEBUG) {
+              // digest of the pair as accepted here: its image, recovered as
+              // on the exact path
+              const uint32_t gj = __float_as_uint(q.w);
+              const double4 pj64 = A.pos64[gj];
+              const double vx = dx - (pj64.x - pi64.x), vy = dy - (pj64.y - pi64.y), vz = dz - (pj64.z - pi64.z);
+              int m[3];
+              for (int d = 0; d < 3; ++d)
+                m[d] = (int)rint(g.Binv[3 * d] * vx + g.Binv[3 * d + 1] * vy + g.Binv[3 * d + 2] * vz);
+              debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, gj, m, wi);
+            }
           }
         };
         for (int dzl = 0; dzl < 3; ++dzl) {

@@ -58,11 +58,12 @@ __device__ inline uint64_t splitmix_out(uint64_t z) {
 
 template <int PREC, bool DEBUG>
 struct Acc {
-  // FP32 modes: per-particle FP32 sums (+ Kahan terms); the energy of the
-  // pairs taken on the FP64 path goes to gu (the half list also keeps their
-  // forces in gx, gy, gz).  FP64 mode uses only the double fields.
-  float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f;
-  float kx = 0.f, ky = 0.f, kz = 0.f, ku = 0.f;
+  // FP32 modes: per-particle FP32 force and virial sums (+ Kahan terms for
+  // the force); the energy of every pair is summed in FP64 in gu (the half
+  // list also keeps the forces of its FP64-path pairs in gx, gy, gz).  FP64
+  // mode uses only the double fields.
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  float kx = 0.f, ky = 0.f, kz = 0.f;
   float w[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   double gx = 0.0, gy = 0.0, gz = 0.0, gu = 0.0;
   double gw[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -120,24 +121,40 @@ __device__ inline void pair64(Acc<PREC, DEBUG>& acc, const Pot64& p, double dx, 
   }
 }
 
+// Pair energy of the FP32 modes, evaluated in FP64 from r^2: the FP32
+// reciprocal r2i of r^2 is refined by one Newton step (relative error about
+// 1e-14).  The shifted energy cancels to zero at the cut-off (for WCA every
+// pair sits near it), where an FP32 evaluation is off by ~1e-8 eps per pair
+// with a bias that does not average out; the 1e-7 energy bound (relative to
+// sum |u_i|) then fails for boxes whose pairs are all near r_c.
+__device__ inline double phi64(const Pot64& p, double r2, float r2i) {
+  double y = (double)r2i;
+  y = fma(y, fma(-r2, y, 1.0), y);
+  const double s2 = p.sig2 * y;
+  const double s6 = s2 * s2 * s2;
+  return fma(s6, fma(p.eps4, s6, -p.eps4), -p.shift);
+}
+
+// one FP32 pair: force and virial in FP32 from the FP32 separation and r2
+// (r^2 rounded once from an FP64 value), energy in FP64 from r2e, the FP64
+// r^2 where the caller has it (else r2 widened)
 template <int PREC, bool DEBUG>
-__device__ inline void pair32(Acc<PREC, DEBUG>& acc, const Pot32& p, float dx, float dy, float dz, float r2) {
+__device__ inline void pair32(Acc<PREC, DEBUG>& acc, const Pot32& p, const Pot64& p64, float dx, float dy, float dz,
+                              float r2, double r2e) {
   const float r2i = __builtin_amdgcn_rcpf(r2);
   const float s2 = p.sig2 * r2i;
   const float s6 = s2 * s2 * s2;
   const float fs = r2i * s6 * fmaf(p.eps48, s6, -p.eps24);
-  const float phi = fmaf(s6, fmaf(p.eps4, s6, -p.eps4), -p.shift);
   if (PREC == 2) {
     kahan_add(acc.fx, acc.kx, -fs * dx);
     kahan_add(acc.fy, acc.ky, -fs * dy);
     kahan_add(acc.fz, acc.kz, -fs * dz);
-    kahan_add(acc.u, acc.ku, phi);
   } else {
     acc.fx = fmaf(-fs, dx, acc.fx);
     acc.fy = fmaf(-fs, dy, acc.fy);
     acc.fz = fmaf(-fs, dz, acc.fz);
-    acc.u += phi;
   }
+  acc.gu += phi64(p64, r2e, r2i);
   const float fdx = fs * dx, fdy = fs * dy;
   acc.w[0] = fmaf(fdx, dx, acc.w[0]);
   acc.w[1] = fmaf(fdy, dy, acc.w[1]);
@@ -188,7 +205,7 @@ template <int PREC, bool DEBUG>
 __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PairList& L) {
   for (const lds_entry* e = L.base; e != L.q; e += PL_STRIDE) {
     const pl_entry v = *e;
-    pair32(acc, A.p32, v.x, v.y, v.z, v.w);
+    pair32(acc, A.p32, A.p64, v.x, v.y, v.z, v.w, (double)v.w);
     acc.pairs += 1;
   }
   L.q = L.base;
@@ -261,7 +278,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           if (r2 < g.rc2_hi64 && j < en && (!CHECK_SELF || j != self)) {
-            if (DEBUG || r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
+            if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: re-evaluate
               // from the FP64 positions exactly as the FP64 mode does
               const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
@@ -279,13 +296,14 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                 if (e2 < A.rclose2_64)
                   pair64(acc, A.p64, ex, ey, ez, e2);
                 else
-                  pair32(acc, A.p32, (float)ex, (float)ey, (float)ez, (float)e2);
+                  pair32(acc, A.p32, A.p64, (float)ex, (float)ey, (float)ez, (float)e2, e2);
                 acc.pairs += 1;
                 debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
               }
             } else {
               *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
               L.q += PL_STRIDE;
+              debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
             }
           }
         }
@@ -310,7 +328,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           if (r2 < g.rc2_hi64 && j < en && j != self) {
-            if (DEBUG || r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
+            if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: re-evaluate
               // from the FP64 positions exactly as the FP64 mode does
               const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
@@ -328,13 +346,14 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                 if (e2 < A.rclose2_64)
                   pair64(acc, A.p64, ex, ey, ez, e2);
                 else
-                  pair32(acc, A.p32, (float)ex, (float)ey, (float)ez, (float)e2);
+                  pair32(acc, A.p32, A.p64, (float)ex, (float)ey, (float)ez, (float)e2, e2);
                 acc.pairs += 1;
                 debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
               }
             } else {
               *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
               L.q += PL_STRIDE;
+              debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
             }
           }
         }
@@ -485,7 +504,7 @@ __device__ inline void acc_energy(const Acc<PREC, DEBUG>& acc, double* v) {
     v[0] = acc.gu;
     for (int k = 0; k < 6; ++k) v[1 + k] = acc.gw[k];
   } else {
-    v[0] = (PREC == 2 ? ((double)acc.u - (double)acc.ku) : (double)acc.u) + acc.gu;
+    v[0] = acc.gu;
     for (int k = 0; k < 6; ++k) v[1 + k] = (double)acc.w[k];
   }
 }

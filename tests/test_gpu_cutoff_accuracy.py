@@ -9,7 +9,7 @@ with r^2 recomputed from the rounded FP32 components about 4 of these
 particles exceed the bound; with r^2 carried from FP64 the worst is 6.7e-6.
 The FP32 paths must keep the per-particle error within
 1e-5 max(sum_j |f_ij|, eps/sigma) for every sweep schedule and both cell
-lists."""
+lists, and the energy within 1e-7 of sum_i |u_i| with no floor."""
 import functools
 
 import numpy as np
@@ -77,9 +77,8 @@ def test_isolated_pairs_near_wca_cutoff(variant, precision, sweep):
     assert cond[i] <= 1e-5, f"{label}: particle {i} force error {cond[i]:.3e}"
     assert np.linalg.norm(g["F"] - r.F) / np.linalg.norm(r.F) <= 1e-5, label
     # energy: the shifted WCA energy also vanishes at r_c (mean |u_i| here is
-    # 0.003 eps), so the relative bound takes an eps floor per pair, as the
-    # force bound takes eps/sigma per particle
-    npair = len(x) // 2
+    # 0.003 eps); the FP32 paths evaluate the pair energy in FP64, so the
+    # plain relative bound holds with no floor
     dU = abs(g["U"] - r.U)
-    assert dU <= 1e-7 * max(np.abs(r.u).sum(), npair), f"{label}: energy error {dU:.3e}"
+    assert dU <= 1e-7 * np.abs(r.u).sum(), f"{label}: energy error {dU:.3e} (sum |u_i| {np.abs(r.u).sum():.3e})"
     assert np.abs(g["W"] - r.W).max() <= 1e-5 * r.fmag.sum(), label

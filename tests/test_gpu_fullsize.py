@@ -9,6 +9,8 @@ Sizes: 1,048,576 LJ particles across the remap of the uniaxial strain
 sweep; 16,777,216 LJ particles on a jittered grid (biaxial, t = T/2, Kahan
 sums); the 512-replica WCA batch (8.9 M particles, a sample of replicas);
 SLLOD steps of the 64-replica LJ batch checked by shadow evaluation."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -104,11 +106,24 @@ def test_lj_4m_ten_bit_radix():
     print(f"lj4M do: max {mx:.2e} rms {rms:.2e}")
 
 
+@functools.lru_cache(maxsize=1)
+def lj16m_whole_box():
+    """the oracle's energy, virial and pair count of the whole 16M box (one
+    FP64 evaluation on all host threads, shared by both variants)"""
+    box = wl.lj_biaxial_grid()
+    x = oracle_positions(box)
+    Lr, Mt, _ = oracle.reduce(box.L0, box.A, box.t, box.automorphisms)
+    full = oracle.forces_cells(x, Lr, box.pot, Mkey=Mt, want_hash=False)
+    return full.U, full.W.copy(), float(np.abs(full.u).sum()), float(full.fmag.sum()), int(full.stats[1])
+
+
 @pytest.mark.parametrize("variant", ["do", "ds"])
 def test_lj_16m_grid_kahan(variant):
     """16,777,216 LJ particles (grid + jitter, biaxial, t = T/2), FP32 offsets
-    with Kahan sums: sampled parity; total force ~ 0 (Newton's third law
-    holds pair by pair in exact arithmetic)."""
+    with Kahan sums: sampled parity; whole-box energy (1e-7 of sum |u_i|; no
+    close pairs here, so every pair takes the FP32 path) and virial against
+    the oracle; total force ~ 0 (Newton's third law holds pair by pair in
+    exact arithmetic)."""
     box = wl.lj_biaxial_grid()
     x = oracle_positions(box)
     g = gpu_box(box, x, variant, "fp32k", debug=True)
@@ -119,7 +134,13 @@ def test_lj_16m_grid_kahan(variant):
     Fsum = g["F"].sum(axis=0)
     assert np.abs(Fsum).max() <= 1e-5 * np.abs(g["F"]).sum(axis=0).max()
     assert g["stats"]["pairs"] > 0 and g["stats"]["max_occupancy"] > 0
-    print(f"lj16M {variant}: max {mx:.2e} rms {rms:.2e}, |sum F| {np.abs(Fsum).max():.3e}")
+    U, W, usum, fsum, npairs = lj16m_whole_box()
+    assert g["stats"]["pairs"] == npairs
+    assert g["stats"]["fp64_pairs"] < 1e-4 * npairs  # the FP32 path carries the energy
+    relU = abs(g["U"] - U) / usum
+    assert relU <= TOL_U["fp32k"], f"lj16M/{variant}: energy error {relU:.3e}"
+    assert np.abs(g["W"] - W).max() <= TOL_F["fp32k"] * fsum
+    print(f"lj16M {variant}: max {mx:.2e} rms {rms:.2e}, |sum F| {np.abs(Fsum).max():.3e}, rel U {relU:.2e}")
 
 
 def test_wca_512_replica_batch():

@@ -74,14 +74,45 @@ def test_lj_uniaxial_strain_sweep_reduced_n(k, variant):
             compare(g, r, prec, label=f"lj_uniaxial/k{k}/{variant}/{prec}/sweep{sweep}")
 
 
-def test_lj_biaxial_grid_jitter_reduced_n():
+@pytest.mark.parametrize("sweep", [0, 1, 3])
+@pytest.mark.parametrize("prec", ["fp32", "fp32k"])
+def test_lj_biaxial_grid_jitter_reduced_n(prec, sweep):
+    """32^3 LJ grid + jitter: no close pairs, so every pair's energy comes
+    from the FP32 paths; energy within 1e-7 of sum |u_i| for every FP32
+    schedule (tiled, per particle, half list)."""
+    if sweep == 3 and prec != "fp32":
+        pytest.skip("the half list runs in FP32 precision only")
     box = wl.lj_biaxial_grid(grid=32)
     x = oracle_positions(box)
     r = run_oracle(box, x)
     for variant in VARS:
-        g = run_gpu(box, x, variant, "fp32k")
-        e = compare(g, r, "fp32k", label=f"lj_biaxial_grid/{variant}")
+        g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
+        e = compare(g, r, prec, label=f"lj_biaxial_grid/{variant}/{prec}/sweep{sweep}")
+        assert g["stats"]["fp64_pairs"] < 1e-3 * g["stats"]["pairs"]
         assert e["rel_U"] < 1e-7
+
+
+@pytest.mark.parametrize("sweep", [0, 1, 3])
+@pytest.mark.parametrize("prec", ["fp32", "fp32k"])
+def test_wca_grid_jitter_energy(prec, sweep):
+    """WCA at rho = 0.8442 on a 32^3 grid + 0.05 jitter (planar flow, t =
+    0.05 T): the grid's nearest neighbours sit at about 1.06 sigma, inside
+    the cut-off, and no pair is close enough for the FP64 path, so the
+    whole energy comes from the FP32 paths.  Energy within 1e-7 of
+    sum |u_i| (no floor) and forces, for every FP32 schedule and both cell
+    lists."""
+    if sweep == 3 and prec != "fp32":
+        pytest.skip("the half list runs in FP32 precision only")
+    box = wl.make_box("planar", 0.5, 32 ** 3, density=0.8442, pot=wl.WCA, t_frac=0.05, seed=3131,
+                      grid=32, jitter_sigma=0.05)
+    x = oracle_positions(box)
+    r = run_oracle(box, x)
+    assert r.stats[1] > 2 * len(x)  # several pairs per particle
+    for variant in VARS:
+        g = run_gpu(box, x, variant, prec, options={SWEEP_OPT: sweep})
+        e = compare(g, r, prec, label=f"wca_grid/{variant}/{prec}/sweep{sweep}")
+        assert g["stats"]["fp64_pairs"] < 1e-2 * g["stats"]["pairs"]
+        print(f"wca grid {variant} {prec} sweep{sweep}: rel U {e['rel_U']:.2e} max F {e['max_cond_F']:.2e}")
 
 
 def test_unreduced_basis_gives_same_pairs():
