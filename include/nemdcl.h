@@ -256,7 +256,10 @@ int ncl_batch_get_lattices(ncl_batch_handle b, double *Lred, int32_t *cells);
  * so steps are not graph-replayed; positions stay unwrapped between rebuilds
  * and are put back into the reduced box at the end.  NCL_E_CAPACITY if a
  * particle has more neighbours than the lists hold (1.5 times the mean of the
- * densest replica plus 24, rounded up to a multiple of 4). */
+ * densest replica plus 24, rounded up to a multiple of 4).  After any error
+ * of a run with a skin, x and p may have advanced by an unknown number of
+ * steps (x possibly unwrapped): the batch forgets its lattices and cells,
+ * and every later call except ncl_batch_set_lattices returns NCL_E_STATE. */
 int ncl_batch_sllod_run(ncl_batch_handle b, double *x, double *p, void *F, double *U, double *W, double h,
                         double mass, int64_t nsteps, int use_graph, double *hist);
 const char *ncl_batch_last_error(ncl_batch_handle b);

@@ -192,48 +192,7 @@ int ncl_set_lattice(ncl_handle h, const double L0[9], const double A[9], double 
   int rc = remap_policy_init(&p, L0, A, naut, aut);
   if (rc == GEOM_E_SINGULAR) return fail(h, NCL_E_LATTICE, "singular L0");
   if (rc != GEOM_OK) return fail(h, NCL_E_LATTICE, "automorphism not unimodular / not diagonalised by L0, or flow incompatible");
-  if (naut == 0) {
-    // no remap: L_t = exp(tA) L0; closed form for diagonal A, else a Taylor
-    // series with scaling and squaring
-    bool diag = true;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        if (i != j && A[3 * i + j] != 0.0) diag = false;
-    double E[9];
-    if (diag) {
-      for (int k = 0; k < 9; ++k) E[k] = 0.0;
-      for (int i = 0; i < 3; ++i) E[4 * i] = exp(t * A[4 * i]);
-    } else {
-      double X[9], big = 0.0;
-      for (int k = 0; k < 9; ++k) {
-        X[k] = t * A[k];
-        big = fmax(big, fabs(X[k]));
-      }
-      int sq = 0;
-      while (big > 0.125 && sq < 64) {
-        big *= 0.5;
-        ++sq;
-      }
-      const double sc = ldexp(1.0, -sq);
-      for (int k = 0; k < 9; ++k) X[k] *= sc;
-      double term[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-      for (int k = 0; k < 9; ++k) E[k] = term[k];
-      for (int q = 1; q <= 24; ++q) {
-        mat_mul(term, X, term);
-        for (int k = 0; k < 9; ++k) {
-          term[k] /= (double)q;
-          E[k] += term[k];
-        }
-      }
-      for (int q = 0; q < sq; ++q) mat_mul(E, E, E);
-    }
-    mat_mul(E, L0, h->Lred);
-    h->coef[0] = h->coef[1] = 0;
-    for (int k = 0; k < 9; ++k) h->Mtot[k] = (k % 4 == 0) ? 1 : 0;
-  } else {
-    remap_at(p, t, h->Lred, h->coef);
-    remap_matrix(p, h->coef, h->Mtot);
-  }
+  reduced_lattice(p, A, t, h->Lred, h->coef, h->Mtot);
   h->pol = p;
   h->t = t;
   h->have_lattice = true;
@@ -620,16 +579,26 @@ int ncl_compute_forces(ncl_handle h, void* F, double* U, double* W) {
     const ncl_ctx::Tuned* t = nullptr;
     for (const auto& e : h->tuned)
       if (e.key == key) t = &e;
-    if (!t) {
-      ncl_ctx::Tuned nt{};
-      const int rc = autotune(h, &A, U, W, &nt);
-      if (rc) return rc;
-      h->tuned.push_back(nt);
-      t = &h->tuned.back();
+    // the autotuner times schedules with a host wait on events, which a
+    // stream under graph capture cannot do: a class first met during a
+    // capture runs the per-particle sweep and is tuned on a later,
+    // uncaptured call
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(h, hipStreamIsCapturing(h->stream, &cap));
+    if (!t && cap != hipStreamCaptureStatusNone) {
+      mode = SWEEP_PARTICLE;
+    } else {
+      if (!t) {
+        ncl_ctx::Tuned nt{};
+        const int rc = autotune(h, &A, U, W, &nt);
+        if (rc) return rc;
+        h->tuned.push_back(nt);
+        t = &h->tuned.back();
+      }
+      h->last = *t;
+      mode = t->mode;
+      for (int k = 0; k < 6; ++k) brick[k] = t->brick[k];
     }
-    h->last = *t;
-    mode = t->mode;
-    for (int k = 0; k < 6; ++k) brick[k] = t->brick[k];
   }
   hipError_t e = sweep_with(h, &A, mode, brick, U, W);
   if (e != hipSuccess) return hip_fail(h, e, "sweep launch");

@@ -539,7 +539,14 @@ int ncl_batch_sllod_run(ncl_batch_handle b, double* x, double* p, void* F, doubl
   BCHK(b, hipMemsetAsync(b->small + 10, 0, 4, st));
   if (b->skin > 0.0) {
     const int code = sllod_run_lists(b, D, A, x, p, F, U, W, h, mass, nsteps, hist, hist_cap, st);
-    if (code != NCL_OK) return code;
+    if (code != NCL_OK) {
+      // steps may have run: x and p are then advanced by an unknown number
+      // of steps (x unwrapped), and the lattices and cells no longer match
+      // them, so the batch needs ncl_batch_set_lattices again
+      b->built = false;
+      b->have_lattice = false;
+      return code;
+    }
   } else {
   BCHK(b, batch_prologue(D, 0, h, st));
   BCHK(b, batch_build(D, x, st));

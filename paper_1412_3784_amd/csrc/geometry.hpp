@@ -279,6 +279,54 @@ NCL_HD void remap_matrix(const RemapPolicy& p, const int64_t* coef, int64_t* Mto
   for (int k = 0; k < 9; ++k) Mtot[k] = R[k];
 }
 
+// Reduced basis at time t for a policy set up by remap_policy_init (host):
+// with automorphisms, the remapped basis L_t M_tot (Sec. 2.2) and its
+// coefficients; without, L_t = exp(tA) L0 itself (Sec. 2.1), in closed form
+// for diagonal A, else by a Taylor series with scaling and squaring.
+inline void reduced_lattice(const RemapPolicy& p, const double* A, double t, double* Lred, int64_t* coef,
+                            int64_t* Mtot) {
+  if (p.naut > 0) {
+    remap_at(p, t, Lred, coef);
+    remap_matrix(p, coef, Mtot);
+    return;
+  }
+  bool diag = true;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (i != j && A[3 * i + j] != 0.0) diag = false;
+  double E[9];
+  if (diag) {
+    for (int k = 0; k < 9; ++k) E[k] = 0.0;
+    for (int i = 0; i < 3; ++i) E[4 * i] = exp(t * A[4 * i]);
+  } else {
+    double X[9], big = 0.0;
+    for (int k = 0; k < 9; ++k) {
+      X[k] = t * A[k];
+      big = fmax(big, fabs(X[k]));
+    }
+    int sq = 0;
+    while (big > 0.125 && sq < 64) {
+      big *= 0.5;
+      ++sq;
+    }
+    const double sc = ldexp(1.0, -sq);
+    for (int k = 0; k < 9; ++k) X[k] *= sc;
+    double term[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    for (int k = 0; k < 9; ++k) E[k] = term[k];
+    for (int q = 1; q <= 24; ++q) {
+      mat_mul(term, X, term);
+      for (int k = 0; k < 9; ++k) {
+        term[k] /= (double)q;
+        E[k] += term[k];
+      }
+    }
+    for (int q = 0; q < sq; ++q) mat_mul(E, E, E);
+  }
+  mat_mul(E, p.L0, Lred);
+  coef[0] = coef[1] = 0;
+  for (int k = 0; k < 9; ++k) Mtot[k] = (k % 4 == 0) ? 1 : 0;
+}
+
 // ---------------------------------------------------------------------------
 // cell geometry of one box (Sec. 4.1 dynamic size, Sec. 4.2 dynamic offset)
 // ---------------------------------------------------------------------------

@@ -3,7 +3,7 @@ trajectories against the FP64 oracle (including a replica that crosses a KR
 remap during the run, which forces a rebuild), the final forces, energy,
 virial and exact pair count against the oracle evaluated on the GPU's final
 positions, rebuilds triggered by displacement with a thin skin, the list
-capacity error, and option errors."""
+capacity error and the state it leaves, and option errors."""
 import numpy as np
 import pytest
 
@@ -157,4 +157,19 @@ def test_lists_capacity_error_and_options():
     with pytest.raises(NclError) as e:
         bt.sllod_run(x, p, 0.0005, 1.0, 2, use_graph=False, history=False)
     assert e.value.code == n.NCL_E_CAPACITY
+    # after a failed run the batch holds no lattice or cells that could be
+    # paired with positions of an unknown step: it refuses until the
+    # lattices are set again, and then works
+    with pytest.raises(NclError) as e:
+        bt.compute_forces()
+    assert e.value.code == n.NCL_E_STATE
+    with pytest.raises(NclError) as e:
+        bt.build_cells(x, "fp32")
+    assert e.value.code == n.NCL_E_STATE
+    bt.set_lattices("do", [b.L0 for b in boxes], [b.A for b in boxes], [b.t for b in boxes],
+                    [b.automorphisms for b in boxes])
+    bt.build_cells(x, "fp32")
+    F, U, W = bt.compute_forces()
+    torch.cuda.synchronize()
+    assert np.isfinite(U.cpu().numpy()).all()
     bt.close()
