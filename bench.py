@@ -1,18 +1,27 @@
 """Benchmark of the deforming-box pair-force path on one GPU.  Prints one JSON line.
 
-Workloads (--workload):
-  plain  (default) 1,048,576 LJ particles (r_c = 2.5, rho = 0.8) under
-         uniaxial elongation (rate 0.5), cycling through 64 strain values
-         t_k = k T / 64 that cross one lattice remap.  One step = set the
-         lattice at t_k, bin into cells, sweep neighbourhoods for forces,
-         energy and virial.  The line also carries the batched form on 512
-         WCA replicas (N log-uniform in [2048, 65536]) against a loop of
-         single-box calls over the same replicas, unless --no-batch.
-  batch  the 512-replica batch alone as the headline.
-  nemd   SLLOD steps (h = 0.002) of 64 LJ replicas, N log-uniform in
-         [262144, 2097152], captured as one HIP graph per step.
-  longrun the long-run neighbourhood experiment of Sec. 5.3 with measured
-         candidate and pair counts (search efficiency of both lists).
+Default run (--workload plain): the headline is the 1,048,576-particle LJ
+workload (r_c = 2.5, rho = 0.8, uniaxial elongation at rate 0.5) cycling
+through 64 strain values t_k = k T / 64 that cross one lattice remap, timed
+with the dynamic-offset list; one step = set the lattice at t_k, bin into
+cells, sweep neighbourhoods for forces, energy and virial.  The same line
+also carries, each under its own key:
+  variants.ds   the same workload with the dynamic-size list;
+  precision_16m 16,777,216 LJ particles on a jittered 256^3 grid (biaxial,
+                rate 0.2, t = T/2), FP32 offsets with Kahan sums, both lists,
+                with the force error of a sample of particles against the
+                FP64 oracle;
+  batched       512 WCA replicas (N log-uniform in [2048, 65536]) in one
+                batched pass, against loops of single-box calls;
+  nemd          1,000 graph-replayed SLLOD steps (h = 0.002) of 64 LJ
+                replicas (N log-uniform in [262144, 2097152]), with the
+                energy-balance drift, the pressure tensor of four replicas
+                against the oracle on the GPU's own states every 100 steps,
+                and the smallest replica against its FP64 oracle trajectory;
+  cpu_baseline  the FP64 oracle on the host (all threads and one thread).
+Legs can be skipped (--no-batch, --no-16m, --no-nemd, --no-cpu-baseline).
+Other headlines: --workload batch | nemd | longrun (the long-run
+neighbourhood experiment of Sec. 5.3 with measured counts).
 
 value = pair interactions / s: interacting pairs (each unordered pair once)
 summed over the timed steps, divided by the wall time of those steps.
@@ -37,20 +46,25 @@ import workloads as wl  # noqa: E402
 # second (one non-packed FP32/FP64 op per lane per cycle); HBM3E 8 TB/s.
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 HBM_PEAK_GBS = 8000.0
-# algorithmic VALU lane-ops: 7 per candidate distance check (3 sub, mul,
-# 2 fma, cmp) and 22 per in-range ordered pair in FP32 (rcp, LJ force and
-# energy, 3 force fma, energy add, 6-component virial)
+# algorithmic VALU lane-ops of the sweep: 7 per candidate distance check
+# (3 sub, mul, 2 fma, cmp) and 40 per evaluation of an in-range pair (rcp,
+# LJ force and energy, force accumulation, 6-component virial, Kahan terms);
+# a full list evaluates every interacting pair from both ends
 OPS_PER_CANDIDATE = 7
-OPS_PER_PAIR = 22
+OPS_PER_PAIR = 40
 # algorithmic HBM bytes per particle of one sweep launch: read the FP32
-# offset (16), the FP64 position for the exact re-evaluations is not counted,
-# perm (4), write F (12 in FP32) and cell_start (~4 per particle)
-SWEEP_BYTES_PER_PARTICLE = 16 + 4 + 12 + 4
-# algorithmic HBM bytes per particle of the cell build (bin pass): bin count
-# (read x 24, write cell and rank 8, count atomic 8), scatter (read cell,
-# rank, cell start 12, write perm 4), per-cell sort of perm (8), gather (read
-# perm 4 and x 24, write FP64 position 32, FP32 offset 16 and residual 16)
-BUILD_BYTES_PER_PARTICLE = 40 + 16 + 8 + 92
+# offset (16) and perm (4), write F (12 in FP32); cell starts are ~0.1-4 B
+# per particle and not counted
+SWEEP_BYTES_PER_PARTICLE = 16 + 4 + 12
+# algorithmic HBM bytes per particle of the cell build (bin pass) of a
+# counting sort: read x for the histogram (24) and again for the scatter
+# (24), write the FP32 offset (16), perm (4) and the cell id (4), plus ~1 B
+# of cell arrays per particle
+BIN_BYTES_PER_PARTICLE = 24 + 24 + 16 + 4 + 4 + 1
+# the bytes per particle of this build's own cell build by its own count:
+# positions read twice, cell keys and indices through the radix sort, the
+# sorted FP64 position, FP32 offset and offset residual written
+BUILD_DESIGN_BYTES_PER_PARTICLE = 156
 
 # HBM traffic of the sweep kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes over this benchmark (default arguments, 3 steps), each
@@ -86,6 +100,10 @@ def parse():
     p.add_argument("--skin", type=float, default=0.0,
                    help="nemd: neighbour-list skin (0: cells rebuilt every step, graph-replayed)")
     p.add_argument("--no-batch", action="store_true", help="plain: skip the batched comparison")
+    p.add_argument("--no-16m", action="store_true", help="plain: skip the 16M precision-form leg")
+    p.add_argument("--no-nemd", action="store_true", help="plain: skip the SLLOD leg")
+    p.add_argument("--no-variants", action="store_true", help="plain: skip the other cell-list variant")
+    p.add_argument("--nemd-steps", type=int, default=1000, help="plain: SLLOD steps of the nemd leg")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-copy-probe", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=3, help="oracle evaluations in the CPU baseline")
@@ -109,8 +127,10 @@ def copy_probe():
     del x, y
 
 
-def roofline_alu(tot_cands, tot_pairs, t_force, steps, kernel, n):
-    ops = OPS_PER_CANDIDATE * tot_cands + OPS_PER_PAIR * 2 * tot_pairs
+def roofline_alu(tot_cands, tot_evals, t_force, steps, kernel, n):
+    """the sweep against the VALU: algorithmic lane-ops (7 per candidate, 40
+    per pair evaluation) over the force call's event time"""
+    ops = OPS_PER_CANDIDATE * tot_cands + OPS_PER_PAIR * tot_evals
     achieved = ops / t_force / 1e9
     traffic = None
     if SWEEP_TRAFFIC["bytes_per_launch"] is not None and SWEEP_TRAFFIC["src_sha"] == sweep_src_sha():
@@ -118,19 +138,32 @@ def roofline_alu(tot_cands, tot_pairs, t_force, steps, kernel, n):
     return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
             "frac": achieved / VALU_PEAK_GOPS, "traffic": traffic, "kernel": kernel,
             "ops_per_launch": ops / steps, "avg_launch_ms": 1e3 * t_force / steps,
+            "ops_count": f"{OPS_PER_CANDIDATE} per candidate + {OPS_PER_PAIR} per pair evaluation",
             "hbm_algorithmic_GBs": SWEEP_BYTES_PER_PARTICLE * n / (t_force / steps) / 1e9,
             "hbm_algorithmic_frac": SWEEP_BYTES_PER_PARTICLE * n / (t_force / steps) / 1e9 / HBM_PEAK_GBS}
 
 
 # ---------------------------------------------------------------------------
-def run_plain(a, out):
+def bin_pass(t_build, n):
+    """the cell build against HBM: algorithmic bytes of a counting-sort build
+    per particle, and this build's own count beside it"""
+    gbs = BIN_BYTES_PER_PARTICLE * n / t_build / 1e9
+    own = BUILD_DESIGN_BYTES_PER_PARTICLE * n / t_build / 1e9
+    return {"bound": "hbm", "bytes_per_particle": BIN_BYTES_PER_PARTICLE, "achieved_GBs": gbs,
+            "peak_GBs": HBM_PEAK_GBS, "frac": gbs / HBM_PEAK_GBS,
+            "design_bytes_per_particle": BUILD_DESIGN_BYTES_PER_PARTICLE, "design_GBs": own,
+            "design_frac": own / HBM_PEAK_GBS, "avg_ms": 1e3 * t_build}
+
+
+def plain_measure(a, variant, boxes, steps, warmup):
+    """1 M LJ strain sweep with one cell-list variant: per-step lattice, bin
+    and force, timed over `steps` steps after `warmup` untimed ones."""
     import torch
     from paper_1412_3784_amd import Handle
     from paper_1412_3784_amd import nemdcl as ncl
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    boxes = [wl.lj_uniaxial_strain(k=k, n=a.n) for k in range(64)]
     b0 = boxes[0]
     h = Handle(0, stream)
     h.set_potential(b0.pot)
@@ -145,7 +178,8 @@ def run_plain(a, out):
         h.set_lattice(b.L0, b.A, b.t, [])          # no remap: L(t) = exp(tA) L0
         Lt, _, _ = h.get_lattice()
         xs.append((s @ torch.from_numpy(Lt).to(dev).T).contiguous())
-    n = a.n
+    del s
+    n = len(b0.frac)
     F = torch.empty((n, 3), dtype=torch.float64 if a.precision == "fp64" else torch.float32, device=dev)
     U = torch.empty(1, dtype=torch.float64, device=dev)
     W = torch.empty(9, dtype=torch.float64, device=dev)
@@ -155,7 +189,7 @@ def run_plain(a, out):
         h.set_lattice(b.L0, b.A, b.t, b.automorphisms)
         if ev is not None:
             ev[0].record(stream)
-        h.build_cells(a.variant, xs[k % 64], a.precision)
+        h.build_cells(variant, xs[k % 64], a.precision)
         if ev is not None:
             ev[1].record(stream)
         h.compute_forces(F, U, W)
@@ -172,48 +206,138 @@ def run_plain(a, out):
         pairs[k], cands[k], halfk[k] = st["pairs"] / 2, st["candidates"], st["sweep"] == ncl.NCL_SWEEP_HALF
         key = {0: "tiled" + "x".join(map(str, st["brick"])), 1: "particle", 3: "half"}[st["sweep"]]
         sched[key] = sched.get(key, 0) + 1
-    for k in range(a.warmup):
+    for k in range(warmup):
         step(k)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(a.steps):
+    for k in range(steps):
         step(k, evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     t_build = sum(e[0].elapsed_time(e[1]) for e in evs) / 1e3
     t_force = sum(e[1].elapsed_time(e[2]) for e in evs) / 1e3
-    ks = [k % 64 for k in range(a.steps)]
+    h.close()
+    del xs, F
+    torch.cuda.empty_cache()
+    ks = [k % 64 for k in range(steps)]
     tot_pairs = float(sum(pairs[k] for k in ks))
     tot_cands = float(sum(cands[k] for k in ks))
     # pair evaluations: twice per interacting pair for full lists, once for the half list
     tot_evals = float(sum(pairs[k] * (1 if halfk[k] else 2) for k in ks))
+    return {
+        "value": tot_pairs / wall, "unit": "pairs/s", "ms_per_step": 1e3 * wall / steps,
+        "ns_per_particle_step": 1e9 * wall / (steps * n),
+        "breakdown_ms": {"build": 1e3 * t_build / steps, "force": 1e3 * t_force / steps},
+        "schedule": sched, "bin_pass": bin_pass(t_build / steps, n),
+        "candidates_per_particle": tot_cands / (steps * n), "search_efficiency": tot_evals / tot_cands,
+        "deterministic": bool(a.deterministic) and a.sweep != "half",
+        "roofline": roofline_alu(tot_cands, tot_evals, t_force, steps,
+                                 f"sweep[{a.sweep}]<{variant},{a.precision}>", n),
+    }
+
+
+def run_plain(a, out):
+    boxes = [wl.lj_uniaxial_strain(k=k, n=a.n) for k in range(64)]
+    n = a.n
+    r = plain_measure(a, a.variant, boxes, a.steps, a.warmup)
     out.update({
         "metric": "pair interactions/s (bin + force, FP32 offsets, 1e-5 force accuracy)",
-        "value": tot_pairs / wall,
+        "value": r["value"],
         "unit": "pairs/s",
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * wall / a.steps,
-        "ns_per_particle_step": 1e9 * wall / (a.steps * n),
+        "ms_per_step": r["ms_per_step"],
+        "ns_per_particle_step": r["ns_per_particle_step"],
         "dtype": {"fp32": "f32 (f64 lattice)", "fp32k": "f32+kahan (f64 lattice)", "fp64": "f64"}[a.precision],
         "config": {"workload": f"lj2.5_uniaxial_rho0.8_N{n}_64strains_{a.variant}", "n": n,
                    "variant": a.variant, "precision": a.precision, "sweep": a.sweep, "rate": 0.5,
                    "density": 0.8, "rc": 2.5},
-        "breakdown_ms": {"build": 1e3 * t_build / a.steps, "force": 1e3 * t_force / a.steps},
-        "schedule": sched,
-        "bin_pass": {"bound": "hbm", "bytes_per_particle": BUILD_BYTES_PER_PARTICLE,
-                     "achieved_GBs": BUILD_BYTES_PER_PARTICLE * n / (t_build / a.steps) / 1e9,
-                     "peak_GBs": HBM_PEAK_GBS,
-                     "frac": BUILD_BYTES_PER_PARTICLE * n / (t_build / a.steps) / 1e9 / HBM_PEAK_GBS},
-        "candidates_per_particle": tot_cands / (a.steps * n),
-        "search_efficiency": tot_evals / tot_cands,
-        "deterministic": bool(a.deterministic) and a.sweep != "half",
-        "roofline": roofline_alu(tot_cands, tot_evals / 2, t_force, a.steps,
-                                 f"sweep[{a.sweep}]<{a.variant},{a.precision}>", n),
     })
-    h.close()
+    for k in ("breakdown_ms", "schedule", "bin_pass", "candidates_per_particle", "search_efficiency",
+              "deterministic", "roofline"):
+        out[k] = r[k]
+    if not a.no_variants:
+        other = "ds" if a.variant == "do" else "do"
+        o = plain_measure(a, other, boxes, a.steps, a.warmup)
+        o["roofline"] = {k: o["roofline"][k] for k in ("achieved", "frac", "avg_launch_ms", "kernel")}
+        o["workload"] = f"lj2.5_uniaxial_rho0.8_N{n}_64strains_{other}"
+        out["variants"] = {other: o}
     return boxes
+
+
+# ---------------------------------------------------------------------------
+def precision_measure(a, steps, nsample=2048):
+    """16,777,216 LJ particles on a jittered grid (biaxial, t = T/2), FP32
+    offsets with Kahan sums, both lists: bin + force timed over `steps`
+    steps; the force error of a seeded sample of particles against the FP64
+    oracle, relative to max(sum_j |f_ij|, eps/sigma) as the parity bound and
+    to |F_i| for information."""
+    import torch
+    import oracle
+    from paper_1412_3784_amd import Handle
+    from paper_1412_3784_amd import nemdcl as ncl
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    box = wl.lj_biaxial_grid()
+    x = box.positions(lattice_at(box, box.t))
+    n = len(x)
+    idx = np.sort(np.random.default_rng(77).choice(n, size=nsample, replace=False))
+    Lr, Mt, _ = oracle.reduce(box.L0, box.A, box.t, box.automorphisms)
+    ref = oracle.forces_cells(x, Lr, box.pot, Mkey=Mt, want_hash=False, subset=idx)
+    xt = torch.from_numpy(x).to(dev)
+    res = {"workload": f"lj2.5_biaxial_rho0.8_grid256_jitter0.05_N{n}_tHalfT_fp32k", "n": n}
+    for variant in ("do", "ds"):
+        h = Handle(0, stream)
+        h.set_potential(box.pot)
+        h.set_option(ncl.NCL_OPT_DETERMINISTIC, 1)
+        h.set_lattice(box.L0, box.A, box.t, box.automorphisms)
+        F = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        U = torch.empty(1, dtype=torch.float64, device=dev)
+        W = torch.empty(9, dtype=torch.float64, device=dev)
+        for _ in range(2):                         # autotuner and warm-up, untimed
+            h.build_cells(variant, xt, "fp32k")
+            h.compute_forces(F, U, W)
+        st = h.stats()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            evs[k][0].record(stream)
+            h.build_cells(variant, xt, "fp32k")
+            evs[k][1].record(stream)
+            h.compute_forces(F, U, W)
+            evs[k][2].record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        t_build = sum(e[0].elapsed_time(e[1]) for e in evs) / 1e3 / steps
+        t_force = sum(e[1].elapsed_time(e[2]) for e in evs) / 1e3 / steps
+        Fs = F[torch.from_numpy(idx).to(dev)].double().cpu().numpy()
+        h.close()
+        del F
+        dF = np.linalg.norm(Fs - ref.F, axis=1)
+        cond = dF / np.maximum(ref.fmag, 1.0)
+        Fn = np.linalg.norm(ref.F, axis=1)
+        pairs = st["pairs"] / 2
+        rf = roofline_alu(st["candidates"], st["pairs"], t_force, 1, f"sweep[auto]<{variant},fp32k>", n)
+        res[variant] = {
+            "value": pairs / wall, "unit": "pairs/s", "ms_per_step": 1e3 * wall,
+            "ns_per_particle_step": 1e9 * wall / n,
+            "breakdown_ms": {"build": 1e3 * t_build, "force": 1e3 * t_force},
+            "candidates_per_particle": st["candidates"] / n, "pairs_per_particle": st["pairs"] / n,
+            "sweep_valu_frac": rf["frac"], "sweep_hbm_algorithmic_frac": rf["hbm_algorithmic_frac"],
+            "bin_pass": bin_pass(t_build, n),
+            "bin_plus_sweep_hbm_algorithmic_frac":
+                (BIN_BYTES_PER_PARTICLE + SWEEP_BYTES_PER_PARTICLE) * n / (t_build + t_force) / 1e9 / HBM_PEAK_GBS,
+            "force_error": {"sample": nsample, "max_rel_to_sum_abs_fij": float(cond.max()),
+                            "rms_rel_to_sum_abs_fij": float(np.sqrt(np.mean(cond ** 2))),
+                            "max_rel_to_abs_Fi": float((dF / Fn).max()),
+                            "rms_rel_to_abs_Fi": float(np.sqrt(np.mean((dF / Fn) ** 2)))},
+        }
+    del xt
+    torch.cuda.empty_cache()
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -325,64 +449,160 @@ def run_batch(a, out):
                    "replicas": len(boxes), "n_total": r["n_total"], "variant": a.variant},
         "breakdown_ms": r["breakdown_ms"], "candidates_per_particle": r["candidates_per_particle"],
         "loop": r["loop"], "loop_4streams": r["loop_4streams"],
-        "roofline": roofline_alu(r["cands"], r["pairs"], r["t_force"], 1, f"kb_sweep<{a.variant},fp32>",
+        "roofline": roofline_alu(r["cands"], 2 * r["pairs"], r["t_force"], 1, f"kb_sweep<{a.variant},fp32>",
                                  r["n_total"]),
     })
     return boxes
 
 
-def run_nemd(a, out):
+def energy_drift(hist, boxes, h):
+    """energy balance H(t) - H(0) + int sum_a A_aa (K_aa + W_aa) dt per
+    replica (zero along exact SLLOD solutions), relative to |H(0)|; hist has
+    shape (steps + 1, R, 8) with rows (t, U, W diag, K diag)"""
+    adiag = np.array([np.diag(b.A) for b in boxes])               # (R, 3)
+    H = 0.5 * hist[:, :, 5:8].sum(-1) + hist[:, :, 1]
+    rate = (adiag[None] * (hist[:, :, 5:8] + hist[:, :, 2:5])).sum(-1)
+    work = np.concatenate([np.zeros((1, len(boxes))), np.cumsum(0.5 * h * (rate[1:] + rate[:-1]), axis=0)])
+    return np.abs(H - H[0] + work).max(axis=0) / np.abs(H[0])
+
+
+def nemd_measure(a, nsteps=1000, chunk=100, nshadow=4, traj_steps=100, skin=0.0):
+    """SLLOD run of the 64-replica LJ batch: nsteps steps in graph-replayed
+    chunks of `chunk` steps (the time of each chunk's call is summed).  The
+    oracle evaluates the forces of the `nshadow` smallest replicas on the
+    GPU's own FP64 states at step 0 and after every chunk (shadow mode), and
+    their pressure tensors P = (sum p p^T / m + W) / V are compared; the
+    smallest replica also runs its own FP64 oracle trajectory for
+    traj_steps steps, compared pointwise at its end and as time averages of
+    the diagonal pressure over the steps.  Returns the result dict and the
+    boxes."""
     import torch
+    import oracle
     from paper_1412_3784_amd import Batch
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     boxes = wl.lj_sllod_batch(replicas=a.replicas or 64)
+    R = len(boxes)
     xs = [b.positions(lattice_at(b, b.t)) for b in boxes]
     ns = [len(v) for v in xs]
     ntot = sum(ns)
+    off = np.concatenate([[0], np.cumsum(ns)])
+    ps = [wl.maxwell_momenta(n_, 1.0, seed=5000 + r) for r, n_ in enumerate(ns)]
+    order = [int(r) for r in np.argsort(ns, kind="stable")]
+    shadow = order[:nshadow] if nshadow > 0 else []
+    r0 = order[0]
+    x0, p0 = xs[r0].copy(), ps[r0].copy()
     x = torch.from_numpy(np.concatenate(xs)).to(dev)
-    p = torch.from_numpy(np.concatenate([wl.maxwell_momenta(n_, 1.0, seed=5000 + r)
-                                         for r, n_ in enumerate(ns)])).to(dev)
-    del xs
+    p = torch.from_numpy(np.concatenate(ps)).to(dev)
+    del xs, ps
     bt = Batch(ns, 0, stream)
     bt.set_potential(boxes[0].pot)
-    if a.skin > 0:
-        bt.set_option(5, a.skin)                  # NCL_OPT_SKIN: neighbour lists
+    if skin > 0:
+        bt.set_option(5, skin)                    # NCL_OPT_SKIN: neighbour lists
     bt.set_lattices("do", [b.L0 for b in boxes], [b.A for b in boxes], [b.t for b in boxes],
                     [b.automorphisms for b in boxes])
     bt.build_cells(x, "fp32")
-    h = 0.002
-    graph = a.skin == 0
-    bt.sllod_run(x, p, h, 1.0, a.warmup, use_graph=graph)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    F, U, W, hist = bt.sllod_run(x, p, h, 1.0, a.steps, use_graph=graph, history=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    h, mass = 0.002, 1.0
+    graph = skin == 0
+    perr = []
+
+    def shadow_check(step, W):
+        """relative pressure-tensor error of the shadow replicas at `step`"""
+        Wg = W.cpu().numpy().reshape(R, 3, 3)
+        for r in shadow:
+            b = boxes[r]
+            sl = slice(off[r], off[r + 1])
+            xr, pr = x[sl].cpu().numpy(), p[sl].cpu().numpy()
+            Lr, _, _ = oracle.reduce(b.L0, b.A, b.t + step * h, b.automorphisms)
+            ref = oracle.forces_cells(xr, Lr, b.pot, want_hash=False)
+            V = abs(np.linalg.det(Lr))
+            K = pr.T @ pr / mass
+            P_or = (K + ref.W) / V
+            P_gp = (K + Wg[r]) / V
+            perr.append({"step": step, "replica": r, "n": ns[r],
+                         "rel_err": float(np.abs(P_gp - P_or).max() / np.abs(P_or).max())})
+
+    F, U, W = bt.compute_forces()
+    if shadow:
+        shadow_check(0, W)
+    hists, wall, done = [], 0.0, 0
+    traj_cmp = None
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, U, W, hist = bt.sllod_run(x, p, h, mass, k, use_graph=graph, history=True)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        hist = hist.cpu().numpy()
+        hists.append(hist if not hists else hist[1:])
+        done += k
+        if shadow:
+            shadow_check(done, W)
+        if done == traj_steps and traj_steps > 0:
+            sl = slice(off[r0], off[r0 + 1])
+            traj_cmp = (x[sl].cpu().numpy(), p[sl].cpu().numpy())
     st = bt.stats()
     bt.close()
-    hist = hist.cpu().numpy()                     # (steps + 1, R, 8)
-    # energy balance H(t) - H(0) + int sum_a A_aa (K_aa + W_aa) dt per replica
-    adiag = np.array([np.diag(b.A) for b in boxes])               # (R, 3)
-    H = 0.5 * hist[:, :, 5:8].sum(-1) + hist[:, :, 1]
-    rate = (adiag[None] * (hist[:, :, 5:8] + hist[:, :, 2:5])).sum(-1)
-    work = np.concatenate([np.zeros((1, len(boxes))), np.cumsum(0.5 * h * (rate[1:] + rate[:-1]), axis=0)])
-    drift = np.abs(H - H[0] + work).max(axis=0) / np.abs(H[0])
-    pairs = st["pairs"] / 2                       # pairs at the last step
+    hist = np.concatenate(hists)                  # (nsteps + 1, R, 8)
+    drift = energy_drift(hist, boxes, h)
+    res = {"value": st["pairs"] / 2 * nsteps / wall, "unit": "pairs/s", "steps": nsteps,
+           "ms_per_step": 1e3 * wall / nsteps, "ns_per_particle_step": 1e9 * wall / (nsteps * ntot),
+           "workload": f"lj2.5_rho0.8_{R}replicas_N{ntot}_sllod_h0.002_{nsteps}steps",
+           "replicas": R, "n_total": ntot, "h": h, "graph_replayed": graph,
+           "energy_balance_rel_drift": {"max": float(drift.max()), "median": float(np.median(drift))},
+           "pairs_note": "pairs/s uses the last step's pair count for every step"}
+    if skin > 0:
+        res["skin"], res["list_rebuilds"] = skin, st.get("list_rebuilds", 0)
+    if perr:
+        res["pressure_tensor_shadow"] = {
+            "replicas": shadow, "steps": sorted({e["step"] for e in perr}),
+            "max_rel_err": max(e["rel_err"] for e in perr),
+            "median_rel_err": float(np.median([e["rel_err"] for e in perr])),
+            "definition": "max_ab |P_gpu - P_oracle| / max_ab |P_oracle|, P = (sum p p^T / m + W) / V, "
+                          "oracle forces on the GPU's FP64 state"}
+    if traj_cmp is not None:
+        b = boxes[r0]
+        t1 = time.perf_counter()
+        xo, po, ho = oracle.sllod(x0, p0, b.L0, b.A, b.t, b.automorphisms, b.pot, h, mass, traj_steps)
+        t_or = time.perf_counter() - t1
+        L = oracle.lattice_at(b.L0, b.A, b.t + traj_steps * h)
+        d = traj_cmp[0] - xo
+        d -= np.round(np.linalg.solve(L, d.T)).T @ L.T    # nearest image
+        V = abs(np.linalg.det(b.L0))
+        hg = hist[:traj_steps + 1, r0]
+        pdiag_g = (hg[:, 2:5] + hg[:, 5:8]) / V
+        pdiag_o = (ho[:, 2:5] + ho[:, 5:8]) / V
+        res["oracle_trajectory"] = {
+            "replica": r0, "n": ns[r0], "steps": traj_steps, "oracle_seconds": t_or,
+            "max_abs_dx_sigma": float(np.abs(d).max()),
+            "max_rel_dp": float(np.abs(traj_cmp[1] - po).max() / np.abs(po).max()),
+            "time_avg_pressure_diag_gpu": pdiag_g.mean(axis=0).tolist(),
+            "time_avg_pressure_diag_oracle": pdiag_o.mean(axis=0).tolist(),
+            "time_avg_pressure_rel_diff": float(np.abs(pdiag_g.mean(0) - pdiag_o.mean(0)).max()
+                                                / np.abs(pdiag_o.mean(0)).max()),
+            "energy_balance_rel_drift_oracle": float(np.abs(oracle.energy_balance(ho, b.A)).max()
+                                                     / abs(0.5 * ho[0, 5:8].sum() + ho[0, 1]))}
+    del x, p
+    torch.cuda.empty_cache()
+    return res, boxes
+
+
+def run_nemd(a, out):
+    r, boxes = nemd_measure(a, nsteps=a.steps, chunk=a.steps, nshadow=0, traj_steps=0, skin=a.skin)
+    graph = r["graph_replayed"]
     out.update({
         "metric": ("pair interactions/s (SLLOD step: bin + force + integrate, graph-replayed, FP32 forces)"
                    if graph else
                    f"pair interactions/s (SLLOD step: neighbour lists with skin {a.skin}, rebuilt when the "
                    "skin bound or a remap requires, + force + integrate, FP32 forces)"),
-        "value": pairs * a.steps / wall, "unit": "pairs/s", "steps": a.steps,
-        "ms_per_step": 1e3 * wall / a.steps, "ns_per_particle_step": 1e9 * wall / (a.steps * ntot),
+        "value": r["value"], "unit": "pairs/s", "steps": a.steps,
+        "ms_per_step": r["ms_per_step"], "ns_per_particle_step": r["ns_per_particle_step"],
         "dtype": "f32 forces, f64 state and lattice",
-        "config": {"workload": f"lj2.5_rho0.8_{len(boxes)}replicas_N{ntot}_sllod_h0.002",
-                   "replicas": len(boxes), "n_total": ntot, "h": h},
-        "energy_balance_rel_drift": {"max": float(drift.max()), "median": float(np.median(drift))},
-        "skin": a.skin, "list_rebuilds": st.get("list_rebuilds", 0),
-        "pairs_note": "pairs/s uses the last step's pair count for every step",
+        "config": {"workload": r["workload"], "replicas": r["replicas"], "n_total": r["n_total"], "h": r["h"]},
+        "energy_balance_rel_drift": r["energy_balance_rel_drift"],
+        "skin": a.skin, "list_rebuilds": r.get("list_rebuilds", 0), "pairs_note": r["pairs_note"],
     })
     return boxes
 
@@ -473,10 +693,22 @@ def main():
     boxes = None
     if a.workload == "plain":
         boxes = run_plain(a, out)
+        if not a.no_16m:
+            log("16M precision leg")
+            out["precision_16m"] = precision_measure(a, max(1, min(a.steps, 10)))
         if not a.no_batch:
-            r = batch_measure(a, wl.wca_replica_batch(replicas=a.replicas or 512), 20)
+            log("batched leg")
+            r = batch_measure(a, wl.wca_replica_batch(replicas=512), 20)
             out["batched"] = {k: v for k, v in r.items() if k not in ("pairs", "cands", "t_force")}
             out["batched"]["workload"] = f"wca_rho0.8442_{r['replicas']}replicas_N{r['n_total']}_{a.variant}"
+            out["batched"]["roofline"] = {
+                k: v for k, v in roofline_alu(r["cands"], 2 * r["pairs"], r["t_force"], 1,
+                                              f"kb_sweep<{a.variant},fp32>", r["n_total"]).items()
+                if k in ("achieved", "frac", "avg_launch_ms", "kernel", "ops_count")}
+        if not a.no_nemd:
+            log("nemd leg")
+            r, _ = nemd_measure(a, nsteps=a.nemd_steps)
+            out["nemd"] = r
     elif a.workload == "batch":
         boxes = run_batch(a, out)
     elif a.workload == "longrun":
@@ -486,27 +718,55 @@ def main():
     if not a.no_copy_probe:
         copy_probe()
     if not a.no_cpu_baseline and a.workload == "plain":
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(boxes, a.cpu_sample)
     print(json.dumps(out), flush=True)
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(boxes, nsample):
-    """The FP64 oracle (plain dynamic-size cell list, all host threads) on a
-    bounded sample of the same workload: nsample strain values at full N."""
+    """The FP64 oracle (plain dynamic-size cell list) on a bounded sample of
+    the same workload at full N: nsample strain values on all host threads,
+    and the first of them again on one thread."""
     import oracle
     ks = [int(round(q * 63 / max(nsample - 1, 1))) for q in range(nsample)]
-    tot_pairs, tot_t = 0.0, 0.0
-    for k in ks:
+
+    def run(k, threads):
         b = boxes[k]
         x = b.positions(oracle.lattice_at(b.L0, b.A, b.t))
         Lr, Mt, _ = oracle.reduce(b.L0, b.A, b.t, b.automorphisms)
         t0 = time.perf_counter()
-        r = oracle.forces_cells(x, Lr, b.pot, want_hash=False)
-        tot_t += time.perf_counter() - t0
-        tot_pairs += r.stats[1] / 2
+        r = oracle.forces_cells(x, Lr, b.pot, want_hash=False, threads=threads)
+        return r.stats[1] / 2, time.perf_counter() - t0
+
+    tot_pairs, tot_t = 0.0, 0.0
+    for k in ks:
+        pr, t = run(k, 0)
+        tot_pairs += pr
+        tot_t += t
+    p1, t1 = run(ks[0], 1)
+    n = len(boxes[0].frac)
     return {"value": tot_pairs / tot_t, "unit": "pairs/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{len(ks)} strain values (k={ks}) of the same workload at full N, FP64 DS cell list",
-            "seconds": tot_t}
+            "seconds": tot_t, "ns_per_particle_step": 1e9 * tot_t / (len(ks) * n),
+            "one_thread": {"value": p1 / t1, "unit": "pairs/s", "cores": 1, "seconds": t1,
+                           "ns_per_particle_step": 1e9 * t1 / n,
+                           "sample": f"strain value k={ks[0]} at full N, one thread"}}
 
 
 if __name__ == "__main__":

@@ -634,10 +634,13 @@ int orc_forces_cells(const double *x, int64_t n, const double *L, const double *
         for (int64_t i = 0; i < n; ++i) members[fill[cell[i]]++] = i; /* stable: index order */
         free(fill);
     }
+    /* thread count for this call only (0: the OpenMP default) */
+    int nt = 1;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #endif
-#pragma omp parallel for schedule(dynamic, 1)
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
     for (int64_t ch = 0; ch < nchunks; ++ch) {
         double Uc = 0.0, Wc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         int64_t cand = 0, inr = 0;
