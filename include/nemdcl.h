@@ -264,6 +264,34 @@ int ncl_batch_sllod_run(ncl_batch_handle b, double *x, double *p, void *F, doubl
                         double mass, int64_t nsteps, int use_graph, double *hist);
 const char *ncl_batch_last_error(ncl_batch_handle b);
 
+/* ---- entry point that allocates nothing ----------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One call
+ * does what ncl_set_lattice + ncl_build_cells + ncl_compute_forces do with the
+ * per-particle sweep (NCL_OPT_SWEEP = 1) and the default options, for a box
+ * of at most NCL_NOALLOC_MAX_N particles whose cell list has at most
+ * NCL_NOALLOC_MAX_CELLS cells; its results are those of that sequence, bit
+ * for bit.  Every scratch array lives in one file-scope device array of the
+ * library (8 MiB per device, held until the process ends); the call makes
+ * no hipMalloc, hipFree or allocating library call and synchronises nothing,
+ * so it can be captured into a graph.
+ *   device, stream  HIP device and stream (hipStream_t) to enqueue on
+ *   L0, A, t, naut, aut  as ncl_set_lattice
+ *   pot             eps, sigma, r_c, shift flag (as ncl_set_potential)
+ *   variant, precision, x, n  as ncl_build_cells (no debug digests)
+ *   F, U, W         as ncl_compute_forces (device, caller-owned)
+ * Returns NCL_E_CAPACITY when n or the cell count exceeds its maximum (nothing
+ * is enqueued), NCL_E_ARG / NCL_E_LATTICE / NCL_E_BOX_TOO_SMALL as the calls it
+ * replaces.  A non-finite position sets *U to NaN (there is no handle to
+ * report it through).  All calls on one device share its array and leave
+ * their contents there: calls that overlap on one device (two streams, or
+ * threads) race and must be ordered by the caller. */
+#define NCL_NOALLOC_MAX_N 65536
+#define NCL_NOALLOC_MAX_CELLS 65536
+int ncl_forces_noalloc(int device, void *stream, const double L0[9], const double A[9], double t, int naut,
+                       const int32_t *aut, const double pot[4], int variant, int precision, const double *x,
+                       int64_t n, void *F, double *U, double *W);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libnemdcl.so")
-SOURCES = ["api.cpp", "api_batch.cpp", "build.hip", "kernels.hip", "half.hip", "batch.hip"]
+SOURCES = ["api.cpp", "api_batch.cpp", "api_noalloc.cpp", "build.hip", "kernels.hip", "half.hip", "batch.hip"]
 HEADERS = ["geometry.hpp", "kernels.hpp", "batch.hpp", "sweep_common.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

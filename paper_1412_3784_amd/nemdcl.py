@@ -34,7 +34,9 @@ EXPORTED = ["ncl_create", "ncl_destroy", "ncl_set_potential", "ncl_set_option", 
             "ncl_batch_create", "ncl_batch_destroy", "ncl_batch_set_potential", "ncl_batch_set_option",
             "ncl_batch_set_lattices", "ncl_batch_build_cells", "ncl_batch_compute_forces",
             "ncl_batch_debug_pairs", "ncl_batch_get_stats", "ncl_batch_get_lattices", "ncl_batch_sllod_run",
-            "ncl_batch_last_error"]
+            "ncl_batch_last_error", "ncl_forces_noalloc"]
+NCL_NOALLOC_MAX_N = 65536
+NCL_NOALLOC_MAX_CELLS = 65536
 
 
 class NclError(RuntimeError):
@@ -82,6 +84,7 @@ def _load():
         "ncl_batch_get_lattices": [P, P, P],
         "ncl_batch_sllod_run": [P, P, P, P, P, P, D, D, I64, I, P],
         "ncl_batch_last_error": [P],
+        "ncl_forces_noalloc": [I, P, P, P, D, I, P, P, I, I, P, I64, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -343,6 +346,24 @@ def ncl_batch_sllod_run(b, x, p, F, U, W, h, mass, nsteps, use_graph, hist=None)
 
 def ncl_batch_last_error(b) -> str:
     return _lib.ncl_batch_last_error(b).decode()
+
+
+def ncl_forces_noalloc(device: int, stream: int, L0, A, t: float, automorphisms, pot, variant: int,
+                       precision: int, x, n: int, F, U, W) -> None:
+    """The entry point that allocates nothing (see include/nemdcl.h): lattice,
+    cells and forces of one box of at most NCL_NOALLOC_MAX_N particles.
+    pot = (eps, sigma, r_c, shift flag); F, U, W are caller-owned device
+    tensors."""
+    import torch
+    auts = list(automorphisms or [])
+    aut = _np(np.concatenate([_np(M, np.int32).reshape(9) for M in auts]), np.int32) if auts else None
+    L0a, Aa, pa = _np(L0, np.float64).reshape(9), _np(A, np.float64).reshape(9), _np(pot, np.float64).reshape(4)
+    code = _lib.ncl_forces_noalloc(int(device), ctypes.c_void_p(stream or None), _ptr(L0a), _ptr(Aa), float(t),
+                                   len(auts), _ptr(aut), _ptr(pa), int(variant), int(precision),
+                                   _dev_ptr(x, torch.float64) if n else None, int(n),
+                                   _dev_ptr(F) if n else None, _dev_ptr(U, torch.float64), _dev_ptr(W, torch.float64))
+    if code != NCL_OK:
+        raise NclError(code, "ncl_forces_noalloc")
 
 
 class Batch:
