@@ -361,7 +361,7 @@ def batch_measure(a, boxes, steps, loop_reps=3):
     U = torch.empty(len(boxes), dtype=torch.float64, device=dev)
     W = torch.empty(9 * len(boxes), dtype=torch.float64, device=dev)
     bt.build_cells(x, "fp32")
-    bt.compute_forces(F, U, W)
+    bt.compute_forces(F, U, W)  # the batched autotuner times the staged and fused schedules here
     st = bt.stats()
     for _ in range(2):
         bt.build_cells(x, "fp32")
@@ -385,7 +385,9 @@ def batch_measure(a, boxes, steps, loop_reps=3):
            "ns_per_particle_step": 1e9 * wall / ntot, "replicas": len(boxes), "n_total": ntot,
            "breakdown_ms": {"build": 1e3 * t_build, "force": 1e3 * t_force},
            "candidates_per_particle": st["candidates"] / ntot, "pairs": pairs, "cands": st["candidates"],
-           "t_force": t_force}
+           "t_force": t_force,
+           "schedule": {1: "staged", 4: "fused"}.get(st["sweep"], str(st["sweep"])),
+           "tune_ms": {"staged": st["tune_ms"][0], "fused": st["tune_ms"][1]}}
     # the same replicas through single-box calls, one after another on one stream
     hs = Handle(0, stream)
     hs.set_potential(boxes[0].pot)
@@ -449,6 +451,7 @@ def run_batch(a, out):
                    "replicas": len(boxes), "n_total": r["n_total"], "variant": a.variant},
         "breakdown_ms": r["breakdown_ms"], "candidates_per_particle": r["candidates_per_particle"],
         "loop": r["loop"], "loop_4streams": r["loop_4streams"],
+        "schedule": r["schedule"], "tune_ms": r["tune_ms"],
         "roofline": roofline_alu(r["cands"], 2 * r["pairs"], r["t_force"], 1, f"kb_sweep<{a.variant},fp32>",
                                  r["n_total"]),
     })

@@ -89,7 +89,20 @@ extern "C" {
                                     3 = half list: each pair evaluated once and
                                     applied to both particles with atomic sums
                                     (NCL_PREC_FP32 only; forces are then not
-                                    bit-identical from run to run)               */
+                                    bit-identical from run to run).
+                                    Batches: 1 = staged launches (lattice
+                                    prologue, cell build, per-particle sweep);
+                                    4 = one persistent fused bin + force launch
+                                    after the prologue: workgroups take one
+                                    replica's whole cell build each, then sweep
+                                    blocks whose replica is built; 2 = autotuned
+                                    (default): the first force pass of each
+                                    variant and precision times both and keeps
+                                    the faster.  The fused schedule (and the
+                                    autotuner) copies the positions at
+                                    ncl_batch_build_cells, which stays the only
+                                    call that reads the caller's array          */
+#define NCL_SWEEP_FUSED 4        /* batch sweep schedule, see NCL_OPT_SWEEP      */
 #define NCL_OPT_SKIN 5           /* batches only: skin (in length units, default 0)
                                     of the neighbour lists that
                                     ncl_batch_sllod_run reuses between rebuilds;
@@ -219,7 +232,8 @@ int ncl_batch_create(ncl_batch_handle *out, int device, void *stream, int32_t nr
 int ncl_batch_destroy(ncl_batch_handle b);
 /* As ncl_set_potential; call before ncl_batch_set_lattices. */
 int ncl_batch_set_potential(ncl_batch_handle b, double eps, double sigma, double rc, int shift_energy);
-/* NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS and NCL_OPT_SKIN. */
+/* NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS, NCL_OPT_SWEEP (1, 2 or 4) and
+ * NCL_OPT_SKIN. */
 int ncl_batch_set_option(ncl_batch_handle b, int option, double value);
 /* Per replica r (host arrays): L0 + 9r, A + 9r (diagonal, traceless), strain
  * time t[r], naut[r] automorphisms at aut + 18r (as in ncl_set_lattice). */

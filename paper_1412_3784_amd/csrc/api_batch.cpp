@@ -34,6 +34,22 @@ struct ncl_batch {
   uint32_t kmax = 0;
   int64_t rebuilds = 0;  // list rebuilds of the last SLLOD run
   bool have_lattice = false, built = false;
+  // schedule of the force pass: staged launches (SWEEP_PARTICLE), one fused
+  // persistent bin + force launch (NCL_SWEEP_FUSED) or the autotuner's
+  // choice (SWEEP_AUTO, timed once per variant and precision)
+  int sweep_mode = SWEEP_AUTO;
+  struct Tuned {
+    int key, mode;
+    float ms[2];  // staged, fused
+  };
+  std::vector<Tuned> tuned;
+  int used_mode = SWEEP_PARTICLE;
+  float used_ms[2] = {-1.0f, -1.0f};
+  bool pending = false;          // fused schedule: cells not built yet, the force pass bins
+  const double* x = nullptr;     // positions of the last build (xcopy for the fused schedule)
+  double* xcopy = nullptr;       // fused schedule: the build's positions, read by the force pass
+  uint32_t* fstate = nullptr;    // fused: queue counter, then one ready flag per replica
+  uint32_t *order = nullptr, *blk_order = nullptr;  // fused: bin order, sweep block order
   std::vector<double> t0;
   // device memory (one allocation per array)
   uint32_t *n_off = nullptr, *slot_off = nullptr, *cell_off = nullptr, *blk_rep = nullptr;
@@ -157,13 +173,65 @@ static void sweep_args(ncl_batch* b, SweepArgs* A, void* F) {
   A->p32.shift = (float)shift;
 }
 
+static int tune_key(const ncl_batch* b) { return b->variant * 4 + b->precision; }
+
+static const ncl_batch::Tuned* tuned_entry(const ncl_batch* b) {
+  for (const auto& t : b->tuned)
+    if (t.key == tune_key(b)) return &t;
+  return nullptr;
+}
+
+// schedule the next force pass runs with
+static int sched_mode(const ncl_batch* b) {
+  if (b->sweep_mode != SWEEP_AUTO) return b->sweep_mode;
+  const ncl_batch::Tuned* t = tuned_entry(b);
+  return t ? t->mode : SWEEP_PARTICLE;
+}
+
+// Batched autotuner: the staged build + sweep against the fused launch, each
+// timed once after an untimed run, with HIP events on the caller's stream;
+// the faster is kept for this variant and precision.  Both leave the same
+// cells and the same forces (the sort order and the sweep are identical).
+static int tune(ncl_batch* b, const SweepArgs& A, double* U, double* W) {
+  const BatchDev D = view(b);
+  hipEvent_t ev[3];
+  for (auto& e : ev) BCHK(b, hipEventCreate(&e));
+  float ms[2] = {0.0f, 0.0f};
+  hipError_t e = hipSuccess;
+  for (int m = 0; m < 2 && e == hipSuccess; ++m)
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      if (rep == 1) e = hipEventRecord(ev[0], b->stream);
+      // the fused schedule pays a copy of the positions at every build: its
+      // cost is timed by copying the copy onto itself (same bytes moved)
+      if (m == 1 && e == hipSuccess) e = batch_copy(b->xcopy, b->xcopy, 3 * b->ntot, b->stream);
+      if (e == hipSuccess) e = batch_prologue(D, 0, 0.0, b->stream);
+      if (m == 0) {
+        if (e == hipSuccess) e = batch_build(D, b->x, b->stream);
+        if (e == hipSuccess) e = batch_sweep(A, D, b->precision, false, U, W, b->stream);
+      } else {
+        if (e == hipSuccess) e = batch_fused(A, D, b->x, b->precision, b->fstate, b->order, b->blk_order, U, W, b->stream);
+      }
+      if (rep == 1 && e == hipSuccess) e = hipEventRecord(ev[1], b->stream);
+      if (rep == 1 && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      if (rep == 1 && e == hipSuccess) e = hipEventElapsedTime(&ms[m], ev[0], ev[1]);
+    }
+  for (auto& q : ev) (void)hipEventDestroy(q);
+  if (e != hipSuccess) return bhip(b, e, "batched autotuner");
+  ncl_batch::Tuned t{tune_key(b), ms[1] < ms[0] ? NCL_SWEEP_FUSED : SWEEP_PARTICLE, {ms[0], ms[1]}};
+  b->tuned.push_back(t);
+  b->used_mode = t.mode;  // the schedule of this workload from now on
+  b->used_ms[0] = ms[0];
+  b->used_ms[1] = ms[1];
+  return NCL_OK;
+}
+
 static void free_all(ncl_batch* b) {
   void* bufs[] = {b->n_off,  b->slot_off, b->cell_off, b->blk_rep, b->pol,     b->t0_d,    b->adiag,
                   b->lred,   b->kpart,    b->partial,  b->geom,    b->small,   b->cell_of, b->rank,
                   b->cstart, b->perm,     b->pos64,    b->pos32,
                   b->wrap,   b->dbgF,     b->rs_va,    b->rs_vb,   b->rs_hist, b->rs_off,
                   b->pcur,   b->pb,       b->vl,       b->ysl,     b->vl_cnt,  b->xb,
-                  b->tb,     b->dmax};
+                  b->tb,     b->dmax,     b->fstate,   b->order,   b->blk_order, b->xcopy};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -217,6 +285,19 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->lred, 9 * (size_t)nrep);
   if (e == hipSuccess) e = dalloc(&b->geom, nrep);
   if (e == hipSuccess) e = dalloc(&b->pcur, 2 * (size_t)nrep);
+  // fused schedule: replicas binned smallest first, their sweep blocks in the
+  // same order (a block's replica is then usually binned when it is taken)
+  std::vector<uint32_t> ord(nrep), bord;
+  for (int r = 0; r < nrep; ++r) ord[r] = (uint32_t)r;
+  std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t c) { return n[a] < n[c]; });
+  bord.reserve(slots / 256);
+  for (uint32_t r : ord)
+    for (uint32_t q = soff[r] / 256; q < soff[r + 1] / 256; ++q) bord.push_back(q);
+  if (e == hipSuccess) e = dalloc(&b->fstate, (size_t)nrep + 1);
+  if (e == hipSuccess) e = dalloc(&b->order, (size_t)nrep);
+  if (e == hipSuccess) e = dalloc(&b->blk_order, bord.size());
+  if (e == hipSuccess) e = hipMemcpy(b->order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !bord.empty()) e = hipMemcpy(b->blk_order, bord.data(), bord.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->n_off, noff.data(), noff.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->slot_off, soff.data(), soff.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && !brep.empty()) e = hipMemcpy(b->blk_rep, brep.data(), brep.size() * 4, hipMemcpyHostToDevice);
@@ -265,6 +346,10 @@ int ncl_batch_set_option(ncl_batch_handle b, int option, double value) {
   } else if (option == NCL_OPT_CLOSE_RADIUS) {
     if (!(value >= 0.0)) return bfail(b, NCL_E_ARG, "close radius must be >= 0");
     b->close_r = value;
+  } else if (option == NCL_OPT_SWEEP) {
+    if (value != 1.0 && value != 2.0 && value != 4.0)
+      return bfail(b, NCL_E_ARG, "batch sweep mode must be 1 (staged), 2 (autotuned) or 4 (fused)");
+    b->sweep_mode = (int)value;
   } else if (option == NCL_OPT_SKIN) {
     if (!(value >= 0.0) || !isfinite(value)) return bfail(b, NCL_E_ARG, "skin must be >= 0");
     if (b->have_lattice) return bfail(b, NCL_E_STATE, "set the skin before ncl_batch_set_lattices");
@@ -367,9 +452,22 @@ int ncl_batch_build_cells(ncl_batch_handle b, const double* x, int precision, in
   if (debug && !b->wrap) BCHK(b, dalloc(&b->wrap, b->nslots));
   b->precision = precision;
   b->debug = debug ? 1 : 0;
+  b->x = x;
+  // The fused schedule bins inside the force pass, and the autotuner's first
+  // force pass builds again: both read a copy of the positions taken here,
+  // so the caller's array is read only by this call, as with the staged
+  // build.  Debug builds are staged.
+  const bool fused = !debug && sched_mode(b) == NCL_SWEEP_FUSED;
+  const bool tuning = !debug && b->sweep_mode == SWEEP_AUTO && !tuned_entry(b);
+  if (fused || tuning) {
+    if (!b->xcopy) BCHK(b, dalloc(&b->xcopy, 3 * b->ntot));
+    BCHK(b, batch_copy(b->xcopy, x, 3 * b->ntot, b->stream));
+    b->x = b->xcopy;
+  }
   BatchDev D = view(b);
   BCHK(b, batch_prologue(D, 0, 0.0, b->stream));
-  BCHK(b, batch_build(D, x, b->stream));
+  b->pending = fused;
+  if (!b->pending) BCHK(b, batch_build(D, x, b->stream));
   b->built = true;
   return NCL_OK;
 }
@@ -380,7 +478,20 @@ int ncl_batch_compute_forces(ncl_batch_handle b, void* F, double* U, double* W) 
   BCHK(b, hipSetDevice(b->device));
   SweepArgs A;
   sweep_args(b, &A, F);
-  BCHK(b, batch_sweep(A, view(b), b->precision, false, U, W, b->stream));
+  const BatchDev D = view(b);
+  if (b->pending) {
+    BCHK(b, batch_fused(A, D, b->x, b->precision, b->fstate, b->order, b->blk_order, U, W, b->stream));
+    b->pending = false;
+    b->used_mode = NCL_SWEEP_FUSED;
+    return NCL_OK;
+  }
+  if (b->sweep_mode == SWEEP_AUTO && !b->debug && !tuned_entry(b)) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    BCHK(b, hipStreamIsCapturing(b->stream, &cap));
+    if (cap == hipStreamCaptureStatusNone) return tune(b, A, U, W);
+  }
+  BCHK(b, batch_sweep(A, D, b->precision, false, U, W, b->stream));
+  b->used_mode = SWEEP_PARTICLE;
   return NCL_OK;
 }
 
@@ -401,6 +512,11 @@ int ncl_batch_debug_pairs(ncl_batch_handle b, int64_t* count, uint64_t* hash) {
 int ncl_batch_get_stats(ncl_batch_handle b, ncl_stats* out) {
   if (!b || !out) return NCL_E_ARG;
   BCHK(b, hipSetDevice(b->device));
+  if (b->built && b->pending) {
+    // fused schedule, force pass not run yet: build the cells now
+    BCHK(b, batch_build(view(b), b->x, b->stream));
+    b->pending = false;
+  }
   if (b->built && b->cstart) BCHK(b, launch_max_occupancy(b->cstart, b->ncells, b->small + 8, b->stream));
   uint32_t w[16];
   BCHK(b, hipMemcpyAsync(w, b->small, sizeof w, hipMemcpyDeviceToHost, b->stream));
@@ -416,6 +532,10 @@ int ncl_batch_get_stats(ncl_batch_handle b, ncl_stats* out) {
   out->fp64_pairs = (int64_t)s[2];
   out->neighbourhood = (int64_t)s[3];
   out->list_rebuilds = b->rebuilds;
+  out->sweep = b->used_mode;
+  for (int k = 0; k < 5; ++k) out->tune_ms[k] = -1.0f;
+  if (const ncl_batch::Tuned* t = tuned_entry(b))
+    for (int k = 0; k < 2; ++k) out->tune_ms[k] = t->ms[k];
   out->max_occupancy = (int32_t)w[8];
   if (w[9]) {
     const int code = (int)w[9];
@@ -588,6 +708,7 @@ int ncl_batch_sllod_run(ncl_batch_handle b, double* x, double* p, void* F, doubl
   BCHK(b, hipMemcpyAsync(b->t0_d, b->t0.data(), b->t0.size() * sizeof(double), hipMemcpyHostToDevice, b->stream));
   BCHK(b, hipMemsetAsync(b->small + 10, 0, 4, b->stream));
   b->built = true;
+  b->pending = false;
   return NCL_OK;
 }
 

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "batch.hpp"
 #include "geometry.hpp"
 #include "kernels.hpp"
@@ -136,11 +138,10 @@ __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
   if (D.wrap) D.wrap[s] = make_int4(img[0], img[1], img[2], 0);
 }
 
-// one thread per slot; the workgroup's replica fixes the geometry
+// the per-particle sweep of one 256-slot block lb; the replica of the block
+// fixes the geometry
 template <int VAR, int PREC, bool DEBUG>
-__global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev D) {  // four waves per SIMD
-  __shared__ SweepSmem sm;
-  const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+__device__ inline void sweep_block(const SweepArgs& A0, const BatchDev& D, uint32_t lb, SweepSmem& sm) {
   const uint32_t r = D.blk_rep[lb];
   const CellGeom& g = D.geom[r];
   SweepArgs A = A0;
@@ -165,6 +166,260 @@ __global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev
   acc_energy(acc, v);
   const uint32_t st4[4] = {acc.cand, acc.pairs, acc.fp64, nbh};
   block_commit(A, lb, v, st4, sm.red);
+}
+
+// one thread per slot
+template <int VAR, int PREC, bool DEBUG>
+__global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev D) {  // four waves per SIMD
+  __shared__ SweepSmem sm;
+  sweep_block<VAR, PREC, DEBUG>(A0, D, xcd_block(blockIdx.x, gridDim.x), sm);
+}
+
+// ---------------------------------------------------------------------------
+// Fused bin + force launch.  Each workgroup takes the next item of a queue
+// when it starts: first one bin item per replica (smallest replicas first),
+// then the sweep items (256-slot blocks) in the same replica order.  A bin item sorts its
+// whole replica inside one workgroup (a stable LSD radix sort of the cell
+// keys whose digits are ranked with wave ballots in LDS; keys and values
+// ping-pong through the replica's range of the staged sort buffers, which
+// stay in L2), writes the replica's cell starts, slot permutation and sorted
+// positions, then releases the replica's ready flag.  A sweep item waits
+// (bounded) for its replica's flag and runs the per-particle sweep of its
+// block.  The wait cannot deadlock: a sweep item is taken only after every
+// bin item has been taken by a running workgroup, and bin items wait on
+// nothing.  Workgroups are not persistent (one item each): a loop over items
+// kept the sweep's invariant state live across items and spilled registers.  The replicas' geometry comes from the lattice prologue launched
+// before, so no workgroup reads geometry written in this launch.
+// ---------------------------------------------------------------------------
+constexpr int FB_SUB = 4;                        // sub-rounds of 64 keys per wave and tile
+constexpr uint32_t FB_TILE = SW_THREADS * FB_SUB;  // keys ranked per tile
+constexpr uint32_t FB_SPIN_LIMIT = 1u << 20;     // ~0.2 s of polling before giving up
+
+struct FusedSmem {
+  uint32_t base[256];       // running output offset of each digit
+  uint32_t wcnt[4][256];    // per-wave digit counts of the current tile
+  uint32_t hist[4][256];    // digit histograms of up to four passes
+  uint32_t item;
+  int32_t wait_ok;
+};
+union FusedLds {
+  SweepSmem sw;
+  FusedSmem fb;
+};
+
+// mask of the lanes of this wave whose digit equals this lane's (valid lanes only)
+__device__ inline uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t eq = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t B = __ballot(bit);
+    eq &= bit ? B : ~B;
+  }
+  return eq;
+}
+
+__device__ inline uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// stable sort of n (key, value) pairs in ka/va by the low nbits of the keys;
+// returns 0 if the result is in ka/va, 1 if in kb/vb
+__device__ int wg_radix_sort(uint32_t* __restrict__ ka, uint32_t* __restrict__ va, uint32_t* __restrict__ kb,
+                             uint32_t* __restrict__ vb, uint32_t n, int nbits, FusedSmem& S) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int npass = (nbits + 7) / 8;
+  if (npass == 0 || n == 0) return 0;
+  // every pass's digit histogram from one read of the keys
+  for (int q = tid; q < 4 * 256; q += SW_THREADS) (&S.hist[0][0])[q] = 0u;
+  __syncthreads();
+  for (uint32_t e = tid; e < n; e += SW_THREADS) {
+    const uint32_t k = ka[e];
+    for (int p = 0; p < npass; ++p) atomicAdd(&S.hist[p][(k >> (8 * p)) & 255u], 1u);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int p = 0; p < npass; ++p) {
+    const uint32_t* ks = cur ? kb : ka;
+    const uint32_t* vs = cur ? vb : va;
+    uint32_t* kd = cur ? ka : kb;
+    uint32_t* vd = cur ? va : vb;
+    const int sh = 8 * p;
+    // exclusive scan of the histogram (wave 0, four digits per lane)
+    if (wid == 0) {
+      uint32_t h[4], sum = 0;
+      for (int q = 0; q < 4; ++q) {
+        h[q] = S.hist[p][4 * lane + q];
+        sum += h[q];
+      }
+      uint32_t incl = sum;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+      }
+      uint32_t run = incl - sum;
+      for (int q = 0; q < 4; ++q) {
+        S.base[4 * lane + q] = run;
+        run += h[q];
+      }
+    }
+    for (int q = tid; q < 4 * 256; q += SW_THREADS) (&S.wcnt[0][0])[q] = 0u;
+    __syncthreads();
+    for (uint32_t t0 = 0; t0 < n; t0 += FB_TILE) {
+      // wave w ranks keys t0 + 256 w + 64 q + lane, q = 0..3, in that order
+      uint32_t key[FB_SUB], val[FB_SUB], dig[FB_SUB], pos[FB_SUB];
+#pragma unroll
+      for (int q = 0; q < FB_SUB; ++q) {
+        const uint32_t e = t0 + (uint32_t)(256 * wid + 64 * q + lane);
+        const bool valid = e < n;
+        key[q] = valid ? ks[e] : 0u;
+        val[q] = valid ? vs[e] : 0u;
+        dig[q] = (key[q] >> sh) & 255u;
+        const uint64_t eq = match_digit(dig[q], valid);
+        const uint32_t before = S.wcnt[wid][dig[q]];  // this wave's earlier keys with the digit
+        pos[q] = valid ? before + lanes_below(eq) : 0xffffffffu;
+        // the highest lane of each digit group advances the wave's count
+        if (valid && (eq >> lane) == 1ull) S.wcnt[wid][dig[q]] = before + (uint32_t)__popcll(eq);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < FB_SUB; ++q) {
+        if (pos[q] != 0xffffffffu) {
+          const uint32_t d = dig[q];
+          uint32_t off = S.base[d] + pos[q];
+          for (int w = 0; w < wid; ++w) off += S.wcnt[w][d];
+          kd[off] = key[q];
+          vd[off] = val[q];
+        }
+      }
+      __syncthreads();
+      {
+        const int d = tid;  // 256 threads, one digit each
+        S.base[d] += ((S.wcnt[0][d] + S.wcnt[1][d]) + S.wcnt[2][d]) + S.wcnt[3][d];
+        S.wcnt[0][d] = S.wcnt[1][d] = S.wcnt[2][d] = S.wcnt[3][d] = 0u;
+      }
+      __syncthreads();
+    }
+    cur ^= 1;
+  }
+  return cur;
+}
+
+// bin replica r inside this workgroup
+__device__ void fused_bin(const BatchDev& D, const double* __restrict__ x, uint32_t r, FusedSmem& S) {
+  const int tid = threadIdx.x;
+  const CellGeom& g = D.geom[r];
+  const uint32_t i0 = D.n_off[r], n = D.n_off[r + 1] - i0;
+  const uint32_t s0 = D.slot_off[r], ns = D.slot_off[r + 1] - s0;
+  const uint32_t cell0 = D.cell_off[r];
+  const uint32_t nc = (uint32_t)g.nc[0] * (uint32_t)g.nc[1] * (uint32_t)g.nc[2];
+  uint32_t* ka = D.cell_of + i0;
+  uint32_t* va = D.rank + i0;
+  uint32_t* kb = D.rs_va + i0;
+  uint32_t* vb = D.rs_vb + i0;
+  // cell keys (replica-local cell ids) and local indices
+  for (uint32_t k = tid; k < n; k += SW_THREADS) {
+    const size_t i = (size_t)i0 + k;
+    const double p[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+    double xw[3];
+    int32_t img[3];
+    bool bad = false;
+    const uint32_t c = locate(g, p, xw, img, &bad);
+    if (bad) atomicOr(D.err, 1);
+    ka[k] = c;
+    va[k] = k;
+  }
+  __syncthreads();
+  const int nbits = nc > 1 ? 32 - __clz((int)(nc - 1)) : 0;
+  const int where = wg_radix_sort(ka, va, kb, vb, n, nbits, S);
+  const uint32_t* sk = where ? kb : ka;
+  const uint32_t* sv = where ? vb : va;
+  // cell starts (global sorted positions, as the staged build writes them):
+  // each first particle of a cell fills the cells from the previous key
+  for (uint32_t s = tid; s <= n; s += SW_THREADS) {
+    const uint32_t lo = s == 0 ? 0u : sk[s - 1] + 1u;
+    const uint32_t hi = s == n ? nc : sk[s];
+    for (uint32_t c = lo; c <= hi && (s == 0 || s == n || sk[s] != sk[s - 1]); ++c) D.cstart[cell0 + c] = i0 + s;
+  }
+  // the rest of the replica's cell capacity, up to the next replica's first
+  // cell, holds the replica's end (as the staged build leaves it)
+  const uint32_t cap = D.cell_off[r + 1] - cell0;
+  for (uint32_t c = nc + 1 + tid; c <= cap; c += SW_THREADS) D.cstart[cell0 + c] = i0 + n;
+  // slots: permutation and sorted positions; padding slots marked
+  for (uint32_t s = tid; s < ns; s += SW_THREADS) {
+    if (s >= n) {
+      D.perm[s0 + s] = PAD_SLOT;
+      continue;
+    }
+    const uint32_t i = i0 + sv[s];
+    D.perm[s0 + s] = i;
+    const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
+    double xw[3];
+    int32_t img[3];
+    bool bad = false;
+    const uint32_t c = locate(g, p, xw, img, &bad);
+    const int a = (int)(c % (uint32_t)g.nc[0]);
+    const int b = (int)((c / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
+    const int cz = (int)(c / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
+    double cen[3];
+    cell_centre(g, a, b, cz, cen);
+    D.pos64[s0 + s] = make_double4(xw[0], xw[1], xw[2], 0.0);
+    D.pos32[s0 + s] = make_float4((float)(xw[0] - cen[0]), (float)(xw[1] - cen[1]), (float)(xw[2] - cen[2]),
+                                  __uint_as_float(c));
+    if (D.wrap) D.wrap[s0 + s] = make_int4(img[0], img[1], img[2], 0);
+  }
+}
+
+template <int VAR, int PREC>
+__global__ void __launch_bounds__(SW_THREADS, 4) kb_fused(SweepArgs A0, BatchDev D, const double* __restrict__ x,
+                                                         uint32_t* __restrict__ queue, uint32_t* __restrict__ ready,
+                                                         const uint32_t* __restrict__ order,
+                                                         const uint32_t* __restrict__ blk_order) {
+  __shared__ FusedLds sm;
+  const uint32_t R = D.nrep, nitems = R + D.nslots / SW_THREADS;
+  // items in the order workgroups start, not by block index
+  if (threadIdx.x == 0) sm.fb.item = atomicAdd(queue, 1u);
+  __syncthreads();
+  // wave-uniform (scalar registers): the geometry and ranges it selects are
+  // then scalar too
+  const uint32_t item = __builtin_amdgcn_readfirstlane(sm.fb.item);
+  __syncthreads();
+  if (item >= nitems) return;  // uniform per workgroup
+  if (item < R) {
+    const uint32_t r = __builtin_amdgcn_readfirstlane(order[item]);
+    // a replica's build is the critical path of its sweep blocks, which may
+    // be spinning on other CUs: its waves issue ahead of the sweep waves
+    // sharing this CU
+    __builtin_amdgcn_s_setprio(3);
+    fused_bin(D, x, r, sm.fb);
+    // publish the replica: every thread's writes, then the flag
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&ready[r], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  const uint32_t lb = __builtin_amdgcn_readfirstlane(blk_order[item - R]);
+  if (threadIdx.x == 0) {
+    const uint32_t r = D.blk_rep[lb];
+    uint32_t spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(&ready[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+      __builtin_amdgcn_s_sleep(8);
+      if (++spins > FB_SPIN_LIMIT) {
+        atomicOr(D.err, 16);
+        ok = 0;
+        break;
+      }
+    }
+    sm.fb.wait_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const bool waited = sm.fb.wait_ok != 0;
+  __syncthreads();
+  if (!waited) return;  // flagged; the replica's forces are not written
+  sweep_block<VAR, PREC, false>(A0, D, lb, sm.sw);
 }
 
 // per replica: U = 1/2 sum u, W = 1/2 sum w over its workgroups, in order;
@@ -691,6 +946,45 @@ hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, boo
     NCL_BSW(VAR_DS, 0) NCL_BSW(VAR_DS, 1) NCL_BSW(VAR_DS, 2)
     NCL_BSW(VAR_DO, 0) NCL_BSW(VAR_DO, 1) NCL_BSW(VAR_DO, 2)
 #undef NCL_BSW
+  }
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0);
+  return hipGetLastError();
+}
+
+__global__ void kb_copy_f64(double* dst, const double* src, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t batch_copy(double* dst, const double* src, uint64_t n, hipStream_t st) {
+  if (n > 0) kb_copy_f64<<<cdivb(n, 256), 256, 0, st>>>(dst, src, n);
+  return hipGetLastError();
+}
+
+template <int VAR, int PREC>
+static hipError_t fused_t(const SweepArgs& A, const BatchDev& D, const double* x, uint32_t* fstate,
+                          const uint32_t* order, const uint32_t* blk_order, hipStream_t st) {
+  // one workgroup per item; each takes the next item from the queue
+  const uint32_t nitems = D.nrep + D.nslots / SW_THREADS;
+  kb_fused<VAR, PREC><<<nitems, SW_THREADS, 0, st>>>(A, D, x, fstate, fstate + 1, order, blk_order);
+  return hipGetLastError();
+}
+
+// fused bin + force of every replica (the lattice prologue must have run):
+// fstate holds the queue counter and one ready flag per replica
+hipError_t batch_fused(const SweepArgs& A, const BatchDev& D, const double* x, int precision, uint32_t* fstate,
+                       const uint32_t* order, const uint32_t* blk_order, double* U, double* W, hipStream_t st) {
+  kb_fill_u32<<<1, 64, 0, st>>>((uint32_t*)A.stats, 8, 0u);
+  kb_fill_u32<<<cdivb(D.nrep + 1, 256), 256, 0, st>>>(fstate, D.nrep + 1, 0u);
+  if (D.nslots > 0) {
+    hipError_t e = hipSuccess;
+    if (D.variant == VAR_DS && precision == 0) e = fused_t<VAR_DS, 0>(A, D, x, fstate, order, blk_order, st);
+    if (D.variant == VAR_DS && precision == 1) e = fused_t<VAR_DS, 1>(A, D, x, fstate, order, blk_order, st);
+    if (D.variant == VAR_DS && precision == 2) e = fused_t<VAR_DS, 2>(A, D, x, fstate, order, blk_order, st);
+    if (D.variant == VAR_DO && precision == 0) e = fused_t<VAR_DO, 0>(A, D, x, fstate, order, blk_order, st);
+    if (D.variant == VAR_DO && precision == 1) e = fused_t<VAR_DO, 1>(A, D, x, fstate, order, blk_order, st);
+    if (D.variant == VAR_DO && precision == 2) e = fused_t<VAR_DO, 2>(A, D, x, fstate, order, blk_order, st);
+    if (e != hipSuccess) return e;
   }
   kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0);
   return hipGetLastError();

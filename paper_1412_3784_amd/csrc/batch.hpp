@@ -48,6 +48,12 @@ hipError_t batch_prologue(const BatchDev& D, int off, double h, hipStream_t st);
 hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st);
 hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, bool debug, double* U, double* W,
                        hipStream_t st);
+// fused bin + force in one persistent launch (see batch.hip); the lattice
+// prologue must precede it
+hipError_t batch_fused(const SweepArgs& A, const BatchDev& D, const double* x, int precision, uint32_t* fstate,
+                       const uint32_t* order, const uint32_t* blk_order, double* U, double* W, hipStream_t st);
+// dst[i] = src[i], i < n (a kernel, so that graph captures record no copy node)
+hipError_t batch_copy(double* dst, const double* src, uint64_t n, hipStream_t st);
 hipError_t batch_kick(const BatchDev& D, double* p, const void* F, bool f64, double h, double mass, int second,
                       hipStream_t st);
 hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st,

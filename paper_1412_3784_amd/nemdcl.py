@@ -23,7 +23,7 @@ NCL_E_HIP, NCL_E_DEVICE_FLAG, NCL_E_STATE = -5, -6, -7
 NCL_DYNAMIC_SIZE, NCL_DYNAMIC_OFFSET = 0, 1
 NCL_PREC_FP64, NCL_PREC_FP32, NCL_PREC_FP32_KAHAN = 0, 1, 2
 NCL_OPT_DO_TIGHT, NCL_OPT_CLOSE_RADIUS, NCL_OPT_BAND, NCL_OPT_SWEEP, NCL_OPT_DETERMINISTIC, NCL_OPT_SKIN = 0, 1, 2, 3, 4, 5
-NCL_SWEEP_TILED, NCL_SWEEP_PARTICLE, NCL_SWEEP_AUTO, NCL_SWEEP_HALF = 0, 1, 2, 3
+NCL_SWEEP_TILED, NCL_SWEEP_PARTICLE, NCL_SWEEP_AUTO, NCL_SWEEP_HALF, NCL_SWEEP_FUSED = 0, 1, 2, 3, 4
 
 VARIANTS = {"ds": NCL_DYNAMIC_SIZE, "do": NCL_DYNAMIC_OFFSET}
 PRECISIONS = {"fp64": NCL_PREC_FP64, "fp32": NCL_PREC_FP32, "fp32k": NCL_PREC_FP32_KAHAN}
@@ -326,7 +326,8 @@ def ncl_batch_get_stats(b) -> dict:
     _bcheck(b, _lib.ncl_batch_get_stats(b, ctypes.byref(s)))
     return {"n": s.n, "variant": s.variant, "precision": s.precision, "max_occupancy": s.max_occupancy,
             "ncells": s.ncells, "candidates": s.candidates, "pairs": s.pairs, "fp64_pairs": s.fp64_pairs,
-            "neighbourhood": s.neighbourhood, "list_rebuilds": s.list_rebuilds}
+            "neighbourhood": s.neighbourhood, "list_rebuilds": s.list_rebuilds,
+            "sweep": s.sweep, "tune_ms": list(s.tune_ms)}
 
 
 def ncl_batch_get_lattices(b, nrep: int):
