@@ -190,6 +190,14 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 // force near its cut-off (|f'| about 75 eps/sigma^2 at r = 1.11 sigma)
 // magnifies to ~1e-5 eps/sigma for an isolated pair.  `q` is the lane's next
 // free entry; the pairs are counted when the list is evaluated.
+//
+// Pairs that need the FP64 path (within the rounding band of d_cut, or
+// closer than the close-pair radius) wait at the other end of the same
+// list, from entry PL_K - 1 down, holding the neighbour's slot and lattice
+// image; they are evaluated when the particle's sweep ends (or when they
+// and the ordinary entries leave no room), all lanes together.  Evaluated
+// where they are met, the wave ran the FP64 path once for every lane that
+// met one (about 0.3 close pairs per particle in a uniform random liquid).
 constexpr int PL_K = 10;
 constexpr int SW_THREADS_P = 256;
 constexpr int PL_STRIDE = SW_THREADS_P;  // in entries
@@ -197,10 +205,44 @@ typedef float pl_entry __attribute__((ext_vector_type(4)));      // (d_x, d_y, d
 typedef __attribute__((address_space(3))) pl_entry lds_entry;  // 32-bit LDS pointer
 struct PairList {
   lds_entry* base;
-  lds_entry* q;
-  __device__ explicit PairList(pl_entry* p) : base((lds_entry*)p), q((lds_entry*)p) {}
+  lds_entry* q;    // next ordinary entry (growing up)
+  lds_entry* top;  // last FP64-path entry (growing down from base + PL_K)
+  __device__ explicit PairList(pl_entry* p)
+      : base((lds_entry*)p), q((lds_entry*)p), top((lds_entry*)p + PL_K * PL_STRIDE) {}
 };
 
+// lattice image of a deferred pair, three 10-bit biased components
+__device__ inline uint32_t pack_image(const int* m) {
+  return ((uint32_t)(m[0] + 512) & 0x3ffu) | (((uint32_t)(m[1] + 512) & 0x3ffu) << 10) |
+         (((uint32_t)(m[2] + 512) & 0x3ffu) << 20);
+}
+
+// a pair within the rounding band or closer than the close-pair radius:
+// decided and evaluated from the FP64 wrapped positions exactly as FP64 mode
+template <int PREC, bool DEBUG>
+__device__ inline void exact_pair(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
+                                  uint32_t j, uint32_t code, const int4& wi) {
+  const int m[3] = {(int)(code & 0x3ffu) - 512, (int)((code >> 10) & 0x3ffu) - 512, (int)((code >> 20) & 0x3ffu) - 512};
+  const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
+  const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
+  const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
+  const double4 ph64 = A.pos64[s];
+  const double xo64 = ph64.x - sx, yo64 = ph64.y - sy, zo64 = ph64.z - sz;
+  const double4 pj64 = A.pos64[j];
+  const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
+  const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+  acc.fp64 += 1;
+  if (e2 < A.rc2) {
+    if (e2 < A.rclose2_64)
+      pair64(acc, A.p64, ex, ey, ez, e2);
+    else
+      pair32(acc, A.p32, A.p64, (float)ex, (float)ey, (float)ez, (float)e2, e2);
+    acc.pairs += 1;
+    debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
+  }
+}
+
+// the lane's ordinary entries
 template <int PREC, bool DEBUG>
 __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PairList& L) {
   for (const lds_entry* e = L.base; e != L.q; e += PL_STRIDE) {
@@ -209,6 +251,28 @@ __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, Pai
     acc.pairs += 1;
   }
   L.q = L.base;
+}
+
+// the lane's FP64-path entries
+template <int PREC, bool DEBUG>
+__device__ inline void flush_exact(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
+                                   const int4& wi, PairList& L) {
+  const lds_entry* end = L.base + PL_K * PL_STRIDE;
+  for (const lds_entry* e = L.top; e != end; e += PL_STRIDE) {
+    const pl_entry v = *e;
+    exact_pair(acc, A, g, s, __float_as_uint(v.x), __float_as_uint(v.y), wi);
+  }
+  L.top = L.base + PL_K * PL_STRIDE;
+}
+
+// room for the next group of four candidates in every lane's list
+template <int PREC, bool DEBUG>
+__device__ inline void make_room(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
+                                 const int4& wi, PairList& L) {
+  if (__ballot(L.q + 4 * PL_STRIDE > L.top) != 0) {
+    flush_list(acc, A, L);
+    if (__ballot(L.q + 4 * PL_STRIDE > L.top) != 0) flush_exact(acc, A, g, s, wi, L);
+  }
 }
 
 // Visit one neighbour cell `cj` seen through lattice image `m` (in the
@@ -279,27 +343,10 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           if (r2 < g.rc2_hi64 && j < en && (!CHECK_SELF || j != self)) {
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
-              // within the rounding band of d_cut, or a close pair: re-evaluate
-              // from the FP64 positions exactly as the FP64 mode does
-              const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
-              const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
-              const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
-              // the home position is re-read here rather than kept in
-              // registers through the loop (this path is rare)
-              const double4 ph64 = A.pos64[s];
-              const double xo64 = ph64.x - sx, yo64 = ph64.y - sy, zo64 = ph64.z - sz;
-              const double4 pj64 = A.pos64[j];
-              const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
-              const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
-              acc.fp64 += 1;
-              if (e2 < A.rc2) {
-                if (e2 < A.rclose2_64)
-                  pair64(acc, A.p64, ex, ey, ez, e2);
-                else
-                  pair32(acc, A.p32, A.p64, (float)ex, (float)ey, (float)ez, (float)e2, e2);
-                acc.pairs += 1;
-                debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
-              }
+              // within the rounding band of d_cut, or a close pair: deferred
+              // to the FP64 path (see flush_exact)
+              L.top -= PL_STRIDE;
+              *L.top = pl_entry{__uint_as_float(j), __uint_as_float(pack_image(m)), 0.0f, 0.0f};
             } else {
               *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
               L.q += PL_STRIDE;
@@ -308,7 +355,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
           }
         }
         // the next group appends at most four entries per lane
-        if (__ballot(L.q > L.base + (PL_K - 4) * PL_STRIDE) != 0) flush_list(acc, A, L);
+        make_room(acc, A, g, s, wi, L);
       }
     };
     if constexpr (!FLAT) {
@@ -329,27 +376,10 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           if (r2 < g.rc2_hi64 && j < en && j != self) {
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
-              // within the rounding band of d_cut, or a close pair: re-evaluate
-              // from the FP64 positions exactly as the FP64 mode does
-              const double sx = g.B[0] * m[0] + g.B[1] * m[1] + g.B[2] * m[2];
-              const double sy = g.B[3] * m[0] + g.B[4] * m[1] + g.B[5] * m[2];
-              const double sz = g.B[6] * m[0] + g.B[7] * m[1] + g.B[8] * m[2];
-              // the home position is re-read here rather than kept in
-              // registers through the loop (this path is rare)
-              const double4 ph64 = A.pos64[s];
-              const double xo64 = ph64.x - sx, yo64 = ph64.y - sy, zo64 = ph64.z - sz;
-              const double4 pj64 = A.pos64[j];
-              const double ex = pj64.x - xo64, ey = pj64.y - yo64, ez = pj64.z - zo64;
-              const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
-              acc.fp64 += 1;
-              if (e2 < A.rc2) {
-                if (e2 < A.rclose2_64)
-                  pair64(acc, A.p64, ex, ey, ez, e2);
-                else
-                  pair32(acc, A.p32, A.p64, (float)ex, (float)ey, (float)ez, (float)e2, e2);
-                acc.pairs += 1;
-                debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
-              }
+              // within the rounding band of d_cut, or a close pair: deferred
+              // to the FP64 path (see flush_exact)
+              L.top -= PL_STRIDE;
+              *L.top = pl_entry{__uint_as_float(j), __uint_as_float(pack_image(m)), 0.0f, 0.0f};
             } else {
               *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
               L.q += PL_STRIDE;
@@ -358,7 +388,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
           }
         }
         // the next group appends at most four entries per lane
-        if (__ballot(L.q > L.base + (PL_K - 4) * PL_STRIDE) != 0) flush_list(acc, A, L);
+        make_room(acc, A, g, s, wi, L);
       }
     }
   }
@@ -454,7 +484,10 @@ __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s
       }
     }
   }
-  if (PREC != 0) flush_list(acc, A, L);
+  if (PREC != 0) {
+    flush_list(acc, A, L);
+    flush_exact(acc, A, g, s, wi, L);
+  }
 }
 
 // per-particle outputs: force rotated back to Cartesian for DO, written in
