@@ -71,7 +71,7 @@ BUILD_DESIGN_BYTES_PER_PARTICLE = 156
 # scaled by the reading of the same counter for a plain 1 GiB elementwise
 # kernel in the same run; see profiles/sweep_particle_do_lj1M_traffic.md.
 # Valid only while the sweep sources hash to src_sha (null otherwise).
-SWEEP_TRAFFIC = {"bytes_per_launch": 114432646, "src_sha": "d06d77ac586d7dcf"}
+SWEEP_TRAFFIC = {"bytes_per_launch": 128376349, "src_sha": "aa410cd6948a302f"}
 SWEEP_SOURCES = ["paper_1412_3784_amd/csrc/sweep_common.hpp", "paper_1412_3784_amd/csrc/kernels.hip",
                  "paper_1412_3784_amd/csrc/kernels.hpp", "paper_1412_3784_amd/csrc/geometry.hpp"]
 

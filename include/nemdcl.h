@@ -98,7 +98,9 @@ extern "C" {
                                     blocks whose replica is built; 2 = autotuned
                                     (default): the first force pass of each
                                     variant and precision times both and keeps
-                                    the faster.  The fused schedule (and the
+                                    the faster (the staged schedule only, when
+                                    a replica holds more than 131,072
+                                    particles).  The fused schedule (and the
                                     autotuner) copies the positions at
                                     ncl_batch_build_cells, which stays the only
                                     call that reads the caller's array          */

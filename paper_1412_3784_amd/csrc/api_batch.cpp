@@ -192,8 +192,22 @@ static int sched_mode(const ncl_batch* b) {
 // timed once after an untimed run, with HIP events on the caller's stream;
 // the faster is kept for this variant and precision.  Both leave the same
 // cells and the same forces (the sort order and the sweep are identical).
+// largest replica the autotuner tries the fused schedule on: one workgroup
+// bins a replica, about 1 ms per 65,536 particles
+constexpr int64_t FUSED_TUNE_MAX_N = 131072;
+
 static int tune(ncl_batch* b, const SweepArgs& A, double* U, double* W) {
   const BatchDev D = view(b);
+  if (*std::max_element(b->n.begin(), b->n.end()) > FUSED_TUNE_MAX_N) {
+    // the fused schedule is not a candidate: the staged pass only
+    BCHK(b, batch_prologue(D, 0, 0.0, b->stream));
+    BCHK(b, batch_build(D, b->x, b->stream));
+    BCHK(b, batch_sweep(A, D, b->precision, false, U, W, b->stream));
+    ncl_batch::Tuned t{tune_key(b), SWEEP_PARTICLE, {-1.0f, -1.0f}};
+    b->tuned.push_back(t);
+    b->used_mode = SWEEP_PARTICLE;
+    return NCL_OK;
+  }
   hipEvent_t ev[3];
   for (auto& e : ev) BCHK(b, hipEventCreate(&e));
   float ms[2] = {0.0f, 0.0f};

@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev
 // ---------------------------------------------------------------------------
 constexpr int FB_SUB = 4;                        // sub-rounds of 64 keys per wave and tile
 constexpr uint32_t FB_TILE = SW_THREADS * FB_SUB;  // keys ranked per tile
-constexpr uint32_t FB_SPIN_LIMIT = 1u << 20;     // ~0.2 s of polling before giving up
+constexpr uint32_t FB_SPIN_LIMIT = 1u << 20;     // polls (at least 0.2 s) before giving up
 
 struct FusedSmem {
   uint32_t base[256];       // running output offset of each digit
