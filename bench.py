@@ -63,15 +63,17 @@ SWEEP_BYTES_PER_PARTICLE = 16 + 4 + 12
 BIN_BYTES_PER_PARTICLE = 24 + 24 + 16 + 4 + 4 + 1
 # the bytes per particle of this build's own cell build by its own count:
 # positions read twice, cell keys and indices through the radix sort, the
-# sorted FP64 position, FP32 offset and offset residual written
-BUILD_DESIGN_BYTES_PER_PARTICLE = 156
+# sorted FP64 position and FP32 offset written (the FP32 offset's residual,
+# 16 more, is written only when a tiled sweep may read it, which the timed
+# steps of the per-particle schedule do not)
+BUILD_DESIGN_BYTES_PER_PARTICLE = 140
 
 # HBM traffic of the sweep kernel per launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes over this benchmark (default arguments, 3 steps), each
 # scaled by the reading of the same counter for a plain 1 GiB elementwise
 # kernel in the same run; see profiles/sweep_particle_do_lj1M_traffic.md.
 # Valid only while the sweep sources hash to src_sha (null otherwise).
-SWEEP_TRAFFIC = {"bytes_per_launch": 128376349, "src_sha": "aa410cd6948a302f"}
+SWEEP_TRAFFIC = {"bytes_per_launch": 128439983, "src_sha": "3c544d42dd25a008"}
 SWEEP_SOURCES = ["paper_1412_3784_amd/csrc/sweep_common.hpp", "paper_1412_3784_amd/csrc/kernels.hip",
                  "paper_1412_3784_amd/csrc/kernels.hpp", "paper_1412_3784_amd/csrc/geometry.hpp"]
 

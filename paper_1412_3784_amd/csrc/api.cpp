@@ -283,6 +283,8 @@ static void choose_brick(ncl_ctx* h, const CellGeom& g, size_t n, uint32_t nc) {
   for (int k = 0; k < 6; ++k) h->brick[k] = h->cand[0][k];
 }
 
+static uint64_t tune_key(const ncl_ctx* h);
+
 int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int precision, int debug) {
   if (!h) return NCL_E_ARG;
   if (variant != NCL_DYNAMIC_SIZE && variant != NCL_DYNAMIC_OFFSET) return fail(h, NCL_E_ARG, "bad variant");
@@ -393,7 +395,19 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   L.perm = h->perm;
   L.pos64 = h->pos64;
   L.pos32 = h->pos32;
-  L.pos32lo = h->pos32lo;
+  // the FP32 residuals are read by the tiled sweep only: skipped when the
+  // force pass of this build cannot be tiled (an explicit other schedule,
+  // or an autotuned class already tuned to another; an untuned class is
+  // timed with tiled candidates).  Options and lattices change only with a
+  // new build, so the choice made here holds for this build's force pass.
+  bool need_lo = h->sweep_mode == SWEEP_TILED;
+  if (h->sweep_mode == SWEEP_AUTO) {
+    need_lo = true;
+    const uint64_t key = tune_key(h);
+    for (const auto& t : h->tuned)
+      if (t.key == key) need_lo = t.mode == SWEEP_TILED;
+  }
+  L.pos32lo = need_lo ? h->pos32lo : nullptr;
   L.wrap = debug ? h->wrap : nullptr;
   L.err = (int*)(h->small + 5);
   hipError_t e = launch_build(L, h->stream);

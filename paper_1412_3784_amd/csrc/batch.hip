@@ -158,7 +158,7 @@ __device__ inline void sweep_block(const SweepArgs& A0, const BatchDev& D, uint3
   if (s < send) {
     if (!skip) {
       PairList L(sm.plist + threadIdx.x);
-      sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
+      sweep_particle<VAR, PREC, DEBUG, true>(A, g, s, acc, nbh, L);
     }
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
   }

@@ -70,6 +70,12 @@ NCL_HD int idiv_floor32(int a, int b) {  // b > 0
   int q = a / b;
   return (q * b > a) ? q - 1 : q;
 }
+// floor(a / b), b > 0, by two comparisons when -b <= a < 2b (a cell index
+// plus or minus a few cells), else by a division
+NCL_HD int idiv_floor_near(int a, int b) {
+  if (a >= -b && a < 2 * b) return (int)(a >= b) - (int)(a < 0);
+  return idiv_floor32(a, b);
+}
 
 // ---------------------------------------------------------------------------
 // reduction of the deforming basis (Sec. 2.2)
@@ -341,6 +347,7 @@ struct CellGeom {
   double cen[9];    // DS: Lred diag(1/c) (cell step vectors as columns); DO: diag(w)
   double ds_delta[27][3];  // DS: Lred diag(1/c) delta for the 27 stencil offsets
   double w[3];      // DO cell widths r_ii / l_i; DS: 1/c_i (fractional cell size)
+  double inv_w[2];  // DO: 1 / w[0], 1 / w[1]
   double grow[2];   // DO: neighbourhood growth (in cells) along x and y
   double rc2_lo64, rc2_hi64;  // per-particle screen: rc^2 minus / plus its rounding band
   int32_t nc[3];    // cells per axis (c_i or l_i)
@@ -410,6 +417,7 @@ NCL_HD int cell_geom_init(CellGeom* g, const double* Lred, const int64_t* Mtot, 
           for (int i = 0; i < 3; ++i)
             g->ds_delta[q][i] = g->cen[3 * i] * dx + g->cen[3 * i + 1] * dy + g->cen[3 * i + 2] * dz;
     g->grow[0] = g->grow[1] = 1.0;
+    g->inv_w[0] = g->inv_w[1] = 0.0;
   } else {
     double Q[9], R[9];
     if (!basis_qr(Lred, Q, R)) return GEOM_E_SINGULAR;
@@ -429,6 +437,8 @@ NCL_HD int cell_geom_init(CellGeom* g, const double* Lred, const int64_t* Mtot, 
       g->w[i] = R[4 * i] / g->nc[i];
       g->cen[4 * i] = g->w[i];
     }
+    g->inv_w[0] = 1.0 / g->w[0];
+    g->inv_w[1] = 1.0 / g->w[1];
     if (!mat_inv(g->B, g->Binv)) return GEOM_E_SINGULAR;
     g->grow[0] = do_tight ? rc / g->w[0] : 1.0;
     g->grow[1] = do_tight ? rc / g->w[1] : 1.0;

@@ -62,7 +62,7 @@ struct BuildLaunch {
   uint32_t *cell_of, *rank, *rs_val, *rs_hist, *rs_off, *cstart, *perm;
   double4* pos64;
   float4* pos32;
-  float4* pos32lo;
+  float4* pos32lo;  // may be null when no tiled sweep reads this build
   int4* wrap;  // may be null
   int* err;
 };

@@ -418,7 +418,7 @@ __device__ inline double warp_sum(double v) {
 // per-particle sweep straight from global memory (used for bricks whose
 // neighbourhood does not fit the LDS tile)
 // ---------------------------------------------------------------------------
-template <int VAR, int PREC, bool DEBUG>
+template <int VAR, int PREC, bool DEBUG, bool DIVFREE = false>
 __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s, Acc<PREC, DEBUG>& acc,
                                uint32_t& nbh, PairList& L) {
   const float4 pi = A.pos32[s];
@@ -442,8 +442,8 @@ __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s
         for (int dx = -1; dx <= 1; ++dx, ++q) {
           const int u[3] = {a + dx, b + dy, c + dz};
           int m[3], w[3];
-          for (int k = 0; k < 3; ++k) {
-            m[k] = idiv_floor32(u[k], g.nc[k]);
+          for (int k = 0; k < 3; ++k) {  // u[k] in [-1, nc[k]]
+            m[k] = (int)(u[k] >= g.nc[k]) - (int)(u[k] < 0);
             w[k] = u[k] - m[k] * g.nc[k];
           }
           const uint32_t cj = (uint32_t)w[0] + (uint32_t)g.nc[0] * ((uint32_t)w[1] + (uint32_t)g.nc[1] * (uint32_t)w[2]);
@@ -453,25 +453,33 @@ __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s
         }
   } else {
     // rectangular cells of the rotated box; layer k (z) is offset by
-    // k r23 in y, row (j, k) by j r12 + k r13 in x
+    // k r23 in y, row (j, k) by j r12 + k r13 in x.  DIVFREE: the image
+    // indices by comparisons and the shifts in cells by the reciprocal
+    // widths (a cell only touched at the range's edge may then be visited
+    // or not; it holds no pair in range); otherwise by divisions.  Which is
+    // faster depends on the kernel's register allocation (measured: the
+    // batched sweep gains 5 %, the single-box sweep loses 27 % to spilled
+    // scalar registers).
     const double w0 = g.w[0], w1 = g.w[1], w2 = g.w[2];
     for (int dz = -1; dz <= 1; ++dz) {
-      const int C = c + dz;
-      const int k = idiv_floor32(C, g.nc[2]);
+      const int C = c + dz;  // in [-1, nc[2]]
+      const int k = DIVFREE ? (int)(C >= g.nc[2]) - (int)(C < 0) : idiv_floor32(C, g.nc[2]);
       const int cz = C - k * g.nc[2];
-      const double fy = -(double)k * g.B[5] / w1;
+      const double fy = DIVFREE ? -(double)k * g.B[5] * g.inv_w[1] : -(double)k * g.B[5] / w1;
       const int B0 = (int)floor(b - g.grow[1] + fy);
       const int B1 = (int)ceil(b + 1 + g.grow[1] + fy) - 1;
       for (int Bq = B0; Bq <= B1; ++Bq) {
-        const int j = idiv_floor32(Bq, g.nc[1]);
+        const int j = DIVFREE ? idiv_floor_near(Bq, g.nc[1]) : idiv_floor32(Bq, g.nc[1]);
         const int by = Bq - j * g.nc[1];
         const double xs = (double)j * g.B[1] + (double)k * g.B[2];
-        const double fx = -xs / w0;
+        const double fx = DIVFREE ? -xs * g.inv_w[0] : -xs / w0;
         const int A0 = (int)floor(a - g.grow[0] + fx);
         const int A1 = (int)ceil(a + 1 + g.grow[0] + fx) - 1;
         const uint32_t rowbase = (uint32_t)g.nc[0] * ((uint32_t)by + (uint32_t)g.nc[1] * (uint32_t)cz);
         // the row's cells A0..A1, one contiguous run per x image i
-        for (int i = idiv_floor32(A0, g.nc[0]); i <= idiv_floor32(A1, g.nc[0]); ++i) {
+        const int i0 = DIVFREE ? idiv_floor_near(A0, g.nc[0]) : idiv_floor32(A0, g.nc[0]);
+        const int i1 = DIVFREE ? idiv_floor_near(A1, g.nc[0]) : idiv_floor32(A1, g.nc[0]);
+        for (int i = i0; i <= i1; ++i) {
           const int axlo = max(A0 - i * g.nc[0], 0), axhi = min(A1 - i * g.nc[0], g.nc[0] - 1);
           const int m[3] = {i, j, k};
           // centre offset of x cell 0 of this image of the row
