@@ -52,7 +52,7 @@ struct ncl_batch {
   uint32_t *order = nullptr, *blk_order = nullptr;  // fused: bin order, sweep block order
   std::vector<double> t0;
   // device memory (one allocation per array)
-  uint32_t *n_off = nullptr, *slot_off = nullptr, *cell_off = nullptr, *blk_rep = nullptr;
+  uint32_t *n_off = nullptr, *slot_off = nullptr, *cell_off = nullptr, *blk_rep = nullptr, *in_rep = nullptr;
   RemapPolicy* pol = nullptr;
   double *t0_d = nullptr, *adiag = nullptr, *lred = nullptr, *kpart = nullptr, *partial = nullptr;
   CellGeom* geom = nullptr;
@@ -106,6 +106,7 @@ static BatchDev view(ncl_batch* b) {
   D.slot_off = b->slot_off;
   D.cell_off = b->cell_off;
   D.blk_rep = b->blk_rep;
+  D.in_rep = b->in_rep;
   D.pol = b->pol;
   D.t0 = b->t0_d;
   D.adiag = b->adiag;
@@ -245,7 +246,7 @@ static void free_all(ncl_batch* b) {
                   b->cstart, b->perm,     b->pos64,    b->pos32,
                   b->wrap,   b->dbgF,     b->rs_va,    b->rs_vb,   b->rs_hist, b->rs_off,
                   b->pcur,   b->pb,       b->vl,       b->ysl,     b->vl_cnt,  b->xb,
-                  b->tb,     b->dmax,     b->fstate,   b->order,   b->blk_order, b->xcopy};
+                  b->tb,     b->dmax,     b->fstate,   b->order,   b->blk_order, b->xcopy, b->in_rep};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
 }
@@ -271,16 +272,22 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   b->ntot = tot;
   b->nslots = slots;
   hipError_t e = hipSetDevice(device);
-  std::vector<uint32_t> noff(nrep + 1), soff(nrep + 1), brep(slots / 256);
+  std::vector<uint32_t> noff(nrep + 1), soff(nrep + 1), brep(slots / 256), irep((tot + 255) / 256);
   noff[0] = soff[0] = 0;
   for (int r = 0; r < nrep; ++r) {
     noff[r + 1] = noff[r] + (uint32_t)n[r];
     soff[r + 1] = soff[r] + (uint32_t)(((n[r] + 255) / 256) * 256);
     for (uint32_t q = soff[r] / 256; q < soff[r + 1] / 256; ++q) brep[q] = (uint32_t)r;
   }
+  // replica of particle 256 q: the last r with noff[r] <= 256 q
+  for (size_t q = 0, r = 0; q < irep.size(); ++q) {
+    while (r + 1 < (size_t)nrep && noff[r + 1] <= 256 * q) ++r;
+    irep[q] = (uint32_t)r;
+  }
   if (e == hipSuccess) e = dalloc(&b->n_off, nrep + 1);
   if (e == hipSuccess) e = dalloc(&b->slot_off, nrep + 1);
   if (e == hipSuccess) e = dalloc(&b->blk_rep, brep.size());
+  if (e == hipSuccess) e = dalloc(&b->in_rep, irep.size());
   if (e == hipSuccess) e = dalloc(&b->small, 16);
   if (e == hipSuccess) e = dalloc(&b->perm, slots);
   if (e == hipSuccess) e = dalloc(&b->pos64, slots);
@@ -315,6 +322,7 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = hipMemcpy(b->n_off, noff.data(), noff.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->slot_off, soff.data(), soff.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess && !brep.empty()) e = hipMemcpy(b->blk_rep, brep.data(), brep.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !irep.empty()) e = hipMemcpy(b->in_rep, irep.data(), irep.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->small, 0, 16 * sizeof(uint32_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
@@ -581,19 +589,31 @@ int ncl_batch_get_lattices(ncl_batch_handle b, double* Lred, int32_t* cells) {
   return NCL_OK;
 }
 
-// One SLLOD step of every replica (the sequence a graph captures).
+// SLLOD steps of every replica, each step's second kick done with the next
+// step's first kick and drift in one pass.  Step n from the forces of step
+// n - 1: lattice at t_n, [second kick of n - 1,] first kick and drift,
+// [observables of n - 1 and the step count,] cells, forces of step n.  The
+// first step of a run has no pending second kick; the steps after it are
+// all alike (the sequence a graph captures, lattice offset 2 since the
+// step count then lags one step behind); the run ends with the last step's
+// second kick and observables.
 static hipError_t sllod_step(ncl_batch* b, const BatchDev& D, const SweepArgs& A, double* x, double* p, void* F,
                              double* U, double* W, double h, double mass, double* hist, uint32_t hist_cap,
-                             hipStream_t st) {
+                             bool first, hipStream_t st) {
   const bool f64 = b->precision == NCL_PREC_FP64;
   hipError_t e;
-  if ((e = batch_kick(D, p, F, f64, h, mass, 0, st)) != hipSuccess) return e;
-  if ((e = batch_prologue(D, 1, h, st)) != hipSuccess) return e;
-  if ((e = batch_drift(D, x, p, h, mass, st)) != hipSuccess) return e;
+  if ((e = batch_prologue(D, first ? 1 : 2, h, st)) != hipSuccess) return e;
+  if ((e = batch_kick_drift(D, x, p, F, f64, h, mass, !first, st)) != hipSuccess) return e;
+  if (!first && (e = batch_observe(D, U, W, h, hist, hist_cap, true, st)) != hipSuccess) return e;
   if ((e = batch_build(D, x, st)) != hipSuccess) return e;
-  if ((e = batch_sweep(A, D, b->precision, false, U, W, st)) != hipSuccess) return e;
-  if ((e = batch_kick(D, p, F, f64, h, mass, 1, st)) != hipSuccess) return e;
-  return batch_observe(D, U, W, h, hist, hist_cap, true, st);
+  return batch_sweep(A, D, b->precision, false, U, W, st);
+}
+
+static hipError_t sllod_finish(ncl_batch* b, const BatchDev& D, double* p, void* F, double* U, double* W, double h,
+                               double mass, double* hist, uint32_t hist_cap, hipStream_t st) {
+  hipError_t e = batch_kick(D, p, F, b->precision == NCL_PREC_FP64, h, mass, 1, st);
+  if (e == hipSuccess) e = batch_observe(D, U, W, h, hist, hist_cap, true, st);
+  return e;
 }
 
 // SLLOD with neighbour lists (skin > 0): each step checks on the device
@@ -633,7 +653,7 @@ static int sllod_run_lists(ncl_batch* b, const BatchDev& D, const SweepArgs& A, 
   for (int64_t k = 0; k < nsteps && e == hipSuccess && code == NCL_OK; ++k) {
     if ((e = batch_kick(D, p, F, f64, h, mass, 0, st)) != hipSuccess) break;
     if ((e = batch_prologue(D, 1, h, st)) != hipSuccess) break;
-    if ((e = batch_drift(D, x, p, h, mass, st, false)) != hipSuccess) break;
+    if ((e = batch_drift(D, x, p, h, mass, st)) != hipSuccess) break;
     if ((e = hipMemsetAsync(D.need, 0, sizeof(uint32_t), st)) != hipSuccess) break;
     if ((e = batch_list_check(D, x, 1, h, b->skin, st)) != hipSuccess) break;
     if ((e = read_need(&need)) != hipSuccess) break;
@@ -687,11 +707,12 @@ int ncl_batch_sllod_run(ncl_batch_handle b, double* x, double* p, void* F, doubl
   BCHK(b, batch_sweep(A, D, b->precision, false, U, W, st));
   BCHK(b, batch_kick(D, p, F, f64, 0.0, mass, 1, st));  // p unchanged; kinetic sums
   BCHK(b, batch_observe(D, U, W, h, hist, hist_cap, false, st));
-  if (use_graph && nsteps > 0) {
+  if (nsteps > 0) BCHK(b, sllod_step(b, D, A, x, p, F, U, W, h, mass, hist, hist_cap, true, st));
+  if (use_graph && nsteps > 1) {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     BCHK(b, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = sllod_step(b, D, A, x, p, F, U, W, h, mass, hist, hist_cap, st);
+    hipError_t ce = sllod_step(b, D, A, x, p, F, U, W, h, mass, hist, hist_cap, false, st);
     hipError_t ee = hipStreamEndCapture(st, &graph);
     if (ce != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -704,15 +725,17 @@ int ncl_batch_sllod_run(ncl_batch_handle b, double* x, double* p, void* F, doubl
       return bhip(b, ie, "hipGraphInstantiate");
     }
     hipError_t le = hipSuccess;
-    for (int64_t k = 0; k < nsteps && le == hipSuccess; ++k) le = hipGraphLaunch(exec, st);
+    for (int64_t k = 1; k < nsteps && le == hipSuccess; ++k) le = hipGraphLaunch(exec, st);
     hipError_t se = hipStreamSynchronize(st);
     (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
     if (le != hipSuccess) return bhip(b, le, "hipGraphLaunch");
     if (se != hipSuccess) return bhip(b, se, "graph replay");
   } else {
-    for (int64_t k = 0; k < nsteps; ++k) BCHK(b, sllod_step(b, D, A, x, p, F, U, W, h, mass, hist, hist_cap, st));
+    for (int64_t k = 1; k < nsteps; ++k)
+      BCHK(b, sllod_step(b, D, A, x, p, F, U, W, h, mass, hist, hist_cap, false, st));
   }
+  if (nsteps > 0) BCHK(b, sllod_finish(b, D, p, F, U, W, h, mass, hist, hist_cap, st));
   }
   // the caller's stream continues after the run
   BCHK(b, hipEventRecord(b->ev_out, st));

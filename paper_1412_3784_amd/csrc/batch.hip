@@ -29,14 +29,13 @@ namespace ncl {
 
 constexpr uint32_t PAD_SLOT = 0xffffffffu;
 
-__device__ inline uint32_t find_rep(const uint32_t* __restrict__ off, uint32_t nrep, uint32_t i) {
-  // last r with off[r] <= i
-  uint32_t lo = 0, hi = nrep - 1;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= i) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+// replica of particle i (input order, or position i of the sorted keys,
+// which are replica-major): the replica of its 256-particle block, then a
+// short forward step (replicas hold far more particles than a block)
+__device__ inline uint32_t rep_of(const BatchDev& D, uint32_t i) {
+  uint32_t r = D.in_rep[i >> 8];
+  while (r + 1 < D.nrep && D.n_off[r + 1] <= i) ++r;
+  return r;
 }
 
 __global__ void kb_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v) {
@@ -79,16 +78,10 @@ __global__ void kb_prologue(BatchDev D, int off, double h) {
 }
 
 __global__ void kb_cell_index(BatchDev D, const double* __restrict__ x) {
-  // the replica of the block's first particle by bisection, then a short
-  // forward step per thread (replicas hold far more particles than a block)
-  __shared__ uint32_t rb;
-  const uint32_t i0 = blockIdx.x * blockDim.x, i = i0 + threadIdx.x;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) D.cstart[D.ncells + 1] = 0u;  // no runs of empty cells queued yet
-  if (threadIdx.x == 0) rb = find_rep(D.n_off, D.nrep, i0);
-  __syncthreads();
   if (i >= D.n) return;
-  uint32_t r = rb;
-  while (r + 1 < D.nrep && D.n_off[r + 1] <= i) ++r;
+  const uint32_t r = rep_of(D, i);
   const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
   double xw[3];
   int32_t img[3];
@@ -104,11 +97,13 @@ __global__ void kb_cell_index(BatchDev D, const double* __restrict__ x) {
 }
 
 // sorted position s (replica-major, cells in order) -> slot in the
-// replica's padded range
-__global__ void kb_place(BatchDev D, const uint32_t* __restrict__ keys) {
+// replica's padded range: the sorted positions n_off[r] .. n_off[r + 1] - 1
+// hold replica r's particles, since every key lies in its replica's cell
+// range (an invalid replica's particles all in its cell 0)
+__global__ void kb_place(BatchDev D) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.n) return;
-  const uint32_t r = find_rep(D.cell_off, D.nrep, keys[s]);
+  const uint32_t r = rep_of(D, s);
   D.perm[s + (D.slot_off[r] - D.n_off[r])] = D.rs_va[s];
 }
 
@@ -535,30 +530,69 @@ __device__ inline void drift_factors(const BatchDev& D, uint32_t r, double h, do
   __syncthreads();
 }
 
-// q <- exp(A h) q + h phi1(A h) p / m in the padded input order; wrapping
-// steps then map q back into the reduced box, list steps leave it unwrapped
-// (until the next rebuild)
-__global__ void kb_drift(BatchDev D, double* __restrict__ x, const double* __restrict__ p, double h, double mass,
-                         int wrap) {
+// q <- exp(A h) q + h phi1(A h) p / m in the padded input order, left
+// unwrapped until the next list rebuild (the cell-list steps drift and wrap
+// in kb_kick_drift)
+__global__ void kb_drift(BatchDev D, double* __restrict__ x, const double* __restrict__ p, double h, double mass) {
   __shared__ double ez[3], hphi[3];
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t r = D.blk_rep[blockIdx.x];
   drift_factors(D, r, h, ez, hphi);
   const uint32_t i = padded_input(D, s, r);
   if (i == PAD_SLOT) return;
-  double q[3];
-  for (int d = 0; d < 3; ++d) q[d] = ez[d] * x[3 * (size_t)i + d] + hphi[d] * p[3 * (size_t)i + d] / mass;
-  if (!wrap) {
-    for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d];
-    return;
+  for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = ez[d] * x[3 * (size_t)i + d] + hphi[d] * p[3 * (size_t)i + d] / mass;
+}
+
+// The end of step n - 1 and the start of step n in one pass (both use the
+// forces of step n - 1): if kick2, p <- (p + h/2 F) exp(-A h/2) with the
+// kinetic partial sums of step n - 1; then p <- p exp(-A h/2) + h/2 F and
+// the drift q <- exp(A h) q + h phi1(A h) p / m into the reduced box of the
+// lattice the prologue set for step n.  The arithmetic is that of a second
+// kick, a first kick and a drift in that order, so the trajectory does not
+// depend on the fusion; it reads x, p and F once and writes x and p once.
+template <typename FT>
+__global__ void kb_kick_drift(BatchDev D, double* __restrict__ x, double* __restrict__ p, const FT* __restrict__ F,
+                              double h, double mass, int kick2) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t r = D.blk_rep[blockIdx.x];
+  const uint32_t i = padded_input(D, s, r);
+  __shared__ double ek[3], ez[3], hphi[3];
+  if (threadIdx.x < 3) ek[threadIdx.x] = exp(-0.5 * h * D.adiag[3 * (size_t)r + threadIdx.x]);
+  drift_factors(D, r, h, ez, hphi);  // synchronises the workgroup
+  double k2[3] = {0.0, 0.0, 0.0};
+  if (i != PAD_SLOT) {
+    double v[3], q[3];
+    for (int d = 0; d < 3; ++d) {
+      const double f = (double)F[3 * (size_t)i + d];
+      v[d] = p[3 * (size_t)i + d];
+      if (kick2) {
+        v[d] = (v[d] + 0.5 * h * f) * ek[d];
+        k2[d] = v[d] * v[d] / mass;
+      }
+      v[d] = v[d] * ek[d] + 0.5 * h * f;
+      p[3 * (size_t)i + d] = v[d];
+    }
+    for (int d = 0; d < 3; ++d) q[d] = ez[d] * x[3 * (size_t)i + d] + hphi[d] * v[d] / mass;
+    double Linv[9], L[9];
+    for (int k = 0; k < 9; ++k) L[k] = D.lred[9 * (size_t)r + k];
+    mat_inv(L, Linv);
+    double n[3];
+    for (int d = 0; d < 3; ++d) n[d] = floor(Linv[3 * d] * q[0] + Linv[3 * d + 1] * q[1] + Linv[3 * d + 2] * q[2]);
+    for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d] - (L[3 * d] * n[0] + L[3 * d + 1] * n[1] + L[3 * d + 2] * n[2]);
   }
-  // back into the reduced box of the new lattice: q - Lred floor(Lred^-1 q)
-  double Linv[9], L[9];
-  for (int k = 0; k < 9; ++k) L[k] = D.lred[9 * (size_t)r + k];
-  mat_inv(L, Linv);
-  double n[3];
-  for (int d = 0; d < 3; ++d) n[d] = floor(Linv[3 * d] * q[0] + Linv[3 * d + 1] * q[1] + Linv[3 * d + 2] * q[2]);
-  for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d] - (L[3 * d] * n[0] + L[3 * d + 1] * n[1] + L[3 * d + 2] * n[2]);
+  if (kick2) {
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int d = 0; d < 3; ++d) {
+      const double t = warp_sum(k2[d]);
+      if (lane == 0) red[wid][d] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+      const int d = threadIdx.x;
+      D.kpart[3 * (size_t)blockIdx.x + d] = ((red[0][d] + red[1][d]) + red[2][d]) + red[3][d];
+    }
+  }
 }
 
 // list steps: the slot-ordered Cartesian copy takes the same affine step
@@ -641,7 +675,7 @@ hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
   if (e == hipSuccess) e = fill_empty_runs(D.cstart, D.ncells, st);
   if (e != hipSuccess) return e;
   if (D.n > 0) {
-    kb_place<<<cdivb(D.n, 256), 256, 0, st>>>(D, keys);
+    kb_place<<<cdivb(D.n, 256), 256, 0, st>>>(D);
     kb_gather<<<cdivb(D.nslots, 256), 256, 0, st>>>(D, x);
   }
   return hipGetLastError();
@@ -671,7 +705,7 @@ __device__ inline uint32_t pack_image(int m0, int m1, int m2) {
 __global__ void kb_wrap(BatchDev D, double* __restrict__ x) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D.n) return;
-  const uint32_t r = find_rep(D.n_off, D.nrep, i);
+  const uint32_t r = rep_of(D, i);
   double L[9], Linv[9];
   for (int k = 0; k < 9; ++k) L[k] = D.lred[9 * (size_t)r + k];
   mat_inv(L, Linv);
@@ -1001,11 +1035,21 @@ hipError_t batch_kick(const BatchDev& D, double* p, const void* F, bool f64, dou
   return hipGetLastError();
 }
 
-hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st,
-                       bool wrap) {
+hipError_t batch_kick_drift(const BatchDev& D, double* x, double* p, const void* F, bool f64, double h, double mass,
+                            bool kick2, hipStream_t st) {
+  const uint32_t nb = D.nslots / SW_THREADS;
+  if (nb == 0) return hipSuccess;
+  if (f64)
+    kb_kick_drift<double><<<nb, SW_THREADS, 0, st>>>(D, x, p, (const double*)F, h, mass, kick2 ? 1 : 0);
+  else
+    kb_kick_drift<float><<<nb, SW_THREADS, 0, st>>>(D, x, p, (const float*)F, h, mass, kick2 ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st) {
   if (D.nslots) {
-    kb_drift<<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D, x, p, h, mass, wrap ? 1 : 0);
-    if (!wrap) kb_drift_slots<<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D, p, h, mass);
+    kb_drift<<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D, x, p, h, mass);
+    kb_drift_slots<<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(D, p, h, mass);
   }
   return hipGetLastError();
 }

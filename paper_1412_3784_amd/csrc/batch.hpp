@@ -18,6 +18,7 @@ struct BatchDev {
   const uint32_t* slot_off;  // [nrep+1] slots (multiples of the workgroup)
   const uint32_t* cell_off;  // [nrep+1] cell capacity offsets
   const uint32_t* blk_rep;   // [nslots / 256] replica of each sweep workgroup
+  const uint32_t* in_rep;    // [ceil(n / 256)] replica of particle 256 b (input and sorted order alike)
   const RemapPolicy* pol;    // [nrep]
   const double* t0;          // [nrep] strain time at step 0
   const double* adiag;       // [nrep*3] diagonal of each flow matrix
@@ -56,8 +57,12 @@ hipError_t batch_fused(const SweepArgs& A, const BatchDev& D, const double* x, i
 hipError_t batch_copy(double* dst, const double* src, uint64_t n, hipStream_t st);
 hipError_t batch_kick(const BatchDev& D, double* p, const void* F, bool f64, double h, double mass, int second,
                       hipStream_t st);
-hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st,
-                       bool wrap = true);
+// list steps: unwrapped drift of x and of the slot-ordered copy
+hipError_t batch_drift(const BatchDev& D, double* x, const double* p, double h, double mass, hipStream_t st);
+// optional second kick of the previous step (with its kinetic sums), first
+// kick and wrapped drift of this step in one pass (see batch.hip)
+hipError_t batch_kick_drift(const BatchDev& D, double* x, double* p, const void* F, bool f64, double h, double mass,
+                            bool kick2, hipStream_t st);
 hipError_t batch_wrap(const BatchDev& D, double* x, hipStream_t st);
 hipError_t batch_list_rebuild(const BatchDev& D, double* x, int off, double h, hipStream_t st);
 hipError_t batch_list_check(const BatchDev& D, const double* x, int off, double h, double skin, hipStream_t st);

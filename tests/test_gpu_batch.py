@@ -263,6 +263,32 @@ def test_sllod_continuation_matches_one_run():
         assert np.allclose(two[k], one[k], rtol=1e-12, atol=1e-12), k
 
 
+def test_sllod_single_steps_and_zero_steps():
+    """Runs of one step (a first step and the last step's second kick, no
+    replayed step) chained three times equal one run of three steps; a run
+    of zero steps leaves x and p unchanged and returns the starting forces,
+    energy and virial."""
+    boxes = nemd_batch()
+    xs, ps = start_state(boxes)
+    one = sllod_gpu(boxes, xs, ps, 0.002, 3, "fp64", use_graph=True, history=False)
+    n = [len(x) for x in xs]
+    cut = np.cumsum([0] + n)
+    cur, bt = sllod_gpu(boxes, xs, ps, 0.002, 1, "fp64", use_graph=True, history=True, close=False)
+    assert cur["hist"].shape[0] == 2
+    for _ in range(2):
+        xs_k = [cur["x"][cut[r]:cut[r + 1]] for r in range(len(n))]
+        ps_k = [cur["p"][cut[r]:cut[r + 1]] for r in range(len(n))]
+        cur, bt = sllod_gpu(boxes, xs_k, ps_k, 0.002, 1, "fp64", use_graph=True, history=False, bt=bt,
+                            close=False)
+    bt.close()
+    for k in ("x", "p", "U", "W"):
+        assert np.allclose(cur[k], one[k], rtol=1e-12, atol=1e-12), k
+    zero = sllod_gpu(boxes, xs, ps, 0.002, 0, "fp64", use_graph=True, history=True)
+    assert (zero["x"] == np.concatenate(xs)).all() and (zero["p"] == np.concatenate(ps)).all()
+    start = sllod_gpu(boxes, xs, ps, 0.002, 1, "fp64", use_graph=False, history=True)
+    assert (zero["hist"][0] == start["hist"][0]).all()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", 2e-6)])
 def test_sllod_matches_oracle_trajectory(precision, tol):
     """40 steps of every replica against the oracle's FP64 trajectory; the
