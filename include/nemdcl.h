@@ -259,8 +259,10 @@ int ncl_batch_get_lattices(ncl_batch_handle b, double *Lred, int32_t *cells);
  * (half kick with stretch, drift, rebuild and forces, half kick), positions
  * x (device, FP64) put back into the reduced box after every drift.  F (FP32
  * or FP64 per the build precision), U and W hold the final forces.  With
- * use_graph != 0 one step is captured as a HIP graph and replayed nsteps
- * times.  hist (device, may be NULL) receives (nsteps + 1) x R records of 8
+ * use_graph != 0 one step is captured as a HIP graph and replayed for all
+ * steps but the first (a step's second half kick is done in one pass with
+ * the next step's first half kick and drift, so the first step and the last
+ * half kick run outside the graph).  hist (device, may be NULL) receives (nsteps + 1) x R records of 8
  * doubles: t, U, W_xx, W_yy, W_zz, K_xx, K_yy, K_zz with K = sum p p^T / m.
  * Afterwards the replicas' strain times have advanced by nsteps h.
  * With NCL_OPT_SKIN = s > 0, forces come from neighbour lists within
