@@ -29,6 +29,7 @@ summed over the timed steps, divided by the wall time of those steps.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -261,6 +262,7 @@ def run_plain(a, out):
         out[k] = r[k]
     if not a.no_variants:
         other = "ds" if a.variant == "do" else "do"
+        gc.collect()
         o = plain_measure(a, other, boxes, a.steps, a.warmup)
         o["roofline"] = {k: o["roofline"][k] for k in ("achieved", "frac", "avg_launch_ms", "kernel")}
         o["workload"] = f"lj2.5_uniaxial_rho0.8_N{n}_64strains_{other}"
@@ -695,14 +697,23 @@ def main():
     out = {"metric": None, "value": None, "unit": None, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": None, "data": "synthetic", "config": {}}
+    # Python's cyclic garbage collector runs only between legs: a full
+    # collection in a process holding torch takes tens of milliseconds, and
+    # one landing inside a timed loop stalls the host that feeds the GPU (a
+    # 35 ms pause in 64 steps of 0.78 ms added 0.5 ms to every step).  Objects
+    # without cycles are still freed at once.
+    gc.collect()
+    gc.disable()
     boxes = None
     if a.workload == "plain":
         boxes = run_plain(a, out)
         if not a.no_16m:
             log("16M precision leg")
+            gc.collect()
             out["precision_16m"] = precision_measure(a, max(1, min(a.steps, 10)))
         if not a.no_batch:
             log("batched leg")
+            gc.collect()
             r = batch_measure(a, wl.wca_replica_batch(replicas=512), 20)
             out["batched"] = {k: v for k, v in r.items() if k not in ("pairs", "cands", "t_force")}
             out["batched"]["workload"] = f"wca_rho0.8442_{r['replicas']}replicas_N{r['n_total']}_{a.variant}"
@@ -712,6 +723,7 @@ def main():
                 if k in ("achieved", "frac", "avg_launch_ms", "kernel", "ops_count")}
         if not a.no_nemd:
             log("nemd leg")
+            gc.collect()
             r, _ = nemd_measure(a, nsteps=a.nemd_steps)
             out["nemd"] = r
     elif a.workload == "batch":
