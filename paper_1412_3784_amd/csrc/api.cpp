@@ -355,7 +355,9 @@ int ncl_build_cells(ncl_handle h, int variant, const double* x, int64_t n, int p
   }
   choose_brick(h, g, (size_t)n, nc);
   {
-    size_t nbr = ((size_t)n + 255) / 256;
+    // one partial slot per sweep workgroup (the per-particle sweep's are the
+    // smallest)
+    size_t nbr = ((size_t)n + SWP_MIN_THREADS - 1) / SWP_MIN_THREADS;
     for (int r = 0; r < h->ncand; ++r)
       nbr = std::max(nbr, (size_t)h->cand[r][3] * h->cand[r][4] * h->cand[r][5]);
     if (nbr + 2 > h->cap_bricks || !h->overflow) {

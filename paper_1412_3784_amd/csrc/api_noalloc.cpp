@@ -50,7 +50,7 @@ struct Layout {
 Layout layout(uint32_t n, uint32_t nc) {
   Layout L;
   const size_t m = n > 0 ? n : 1;
-  L.nblk = (uint32_t)((m + 255) / 256);
+  L.nblk = (uint32_t)((m + SWP_MIN_THREADS - 1) / SWP_MIN_THREADS);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;

@@ -133,17 +133,18 @@ __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
   if (D.wrap) D.wrap[s] = make_int4(img[0], img[1], img[2], 0);
 }
 
-// the per-particle sweep of one 256-slot block lb; the replica of the block
-// fixes the geometry
-template <int VAR, int PREC, bool DEBUG>
-__device__ inline void sweep_block(const SweepArgs& A0, const BatchDev& D, uint32_t lb, SweepSmem& sm) {
-  const uint32_t r = D.blk_rep[lb];
+// the per-particle sweep of one BT-slot block lb (BT divides 256, the
+// replicas' slot padding); the replica of the block fixes the geometry
+template <int VAR, int PREC, bool DEBUG, int BT = SW_THREADS>
+__device__ inline void sweep_block(const SweepArgs& A0, const BatchDev& D, uint32_t lb, SweepSmemT<BT>& sm) {
+  static_assert(256 % BT == 0, "blocks of a replica's padded slots");
+  const uint32_t r = D.blk_rep[lb / (256 / BT)];
   const CellGeom& g = D.geom[r];
   SweepArgs A = A0;
   A.cell0 = D.cell_off[r];
   A.pad = (int32_t)(D.slot_off[r] - D.n_off[r]);
   A.jbase = D.n_off[r];
-  const uint32_t s = lb * SW_THREADS + threadIdx.x;
+  const uint32_t s = lb * BT + threadIdx.x;
   const uint32_t send = D.slot_off[r] + (D.n_off[r + 1] - D.n_off[r]);
   Acc<PREC, DEBUG> acc;
   uint32_t nbh = 0;
@@ -152,7 +153,7 @@ __device__ inline void sweep_block(const SweepArgs& A0, const BatchDev& D, uint3
   const bool skip = g.variant < 0 || (D.err[0] & 1) != 0;
   if (s < send) {
     if (!skip) {
-      PairList L(sm.plist + threadIdx.x);
+      PairListS<BT> L(sm.plist + threadIdx.x);
       sweep_particle<VAR, PREC, DEBUG, true>(A, g, s, acc, nbh, L);
     }
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
@@ -160,14 +161,16 @@ __device__ inline void sweep_block(const SweepArgs& A0, const BatchDev& D, uint3
   double v[7];
   acc_energy(acc, v);
   const uint32_t st4[4] = {acc.cand, acc.pairs, acc.fp64, nbh};
-  block_commit(A, lb, v, st4, sm.red);
+  block_commit<BT / 64>(A, lb, v, st4, sm.red);
 }
 
-// one thread per slot
+// one thread per slot, workgroups of swp_threads(VAR) lanes (one partial
+// slot each), four waves per SIMD
 template <int VAR, int PREC, bool DEBUG>
-__global__ void __launch_bounds__(SW_THREADS, 4) kb_sweep(SweepArgs A0, BatchDev D) {  // four waves per SIMD
-  __shared__ SweepSmem sm;
-  sweep_block<VAR, PREC, DEBUG>(A0, D, xcd_block(blockIdx.x, gridDim.x), sm);
+__global__ void __launch_bounds__(swp_threads(VAR), 4) kb_sweep(SweepArgs A0, BatchDev D) {
+  constexpr int BT = swp_threads(VAR);
+  __shared__ SweepSmemT<BT> sm;
+  sweep_block<VAR, PREC, DEBUG, BT>(A0, D, xcd_block(blockIdx.x, gridDim.x), sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,14 +425,21 @@ __global__ void __launch_bounds__(SW_THREADS, 4) kb_fused(SweepArgs A0, BatchDev
 // cart: the partials are already Cartesian (neighbour-list forces), so the
 // dynamic-offset rotation back from the cell frame is skipped
 __global__ void kb_finalize(BatchDev D, const double* __restrict__ partial, double* __restrict__ U,
-                            double* __restrict__ W, unsigned long long* __restrict__ stats, int cart) {
+                            double* __restrict__ W, unsigned long long* __restrict__ stats, int cart, uint32_t bt) {
   __shared__ double red[4][PART_STRIDE];
   const uint32_t r = blockIdx.x;
-  const uint32_t b0 = D.slot_off[r] / SW_THREADS, b1 = D.slot_off[r + 1] / SW_THREADS;
+  // per 256-slot block: its bt-slot partials summed in the order a 256-lane
+  // workgroup sums its waves, so both block sizes give the same sums
+  const uint32_t b0 = D.slot_off[r] / 256, b1 = D.slot_off[r + 1] / 256, sub = 256 / bt;
   double v[PART_STRIDE] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (uint32_t b = b0 + threadIdx.x; b < b1; b += blockDim.x)
     for (int k = 0; k < PART_STRIDE; ++k)
-      if (k != 7) v[k] += partial[PART_STRIDE * (size_t)b + k];
+      if (k != 7) {
+        const double* pb = partial + PART_STRIDE * (size_t)b * sub + k;
+        double t = pb[0];
+        for (uint32_t q = 1; q < sub; ++q) t += pb[PART_STRIDE * q];
+        v[k] += t;
+      }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < PART_STRIDE; ++k) {
     const double t = warp_sum(v[k]);
@@ -965,7 +975,7 @@ __global__ void __launch_bounds__(SW_THREADS) kb_list_force(SweepArgs A, BatchDe
 
 template <int VAR, int PREC, bool DEBUG>
 static void bsweep_t(const SweepArgs& A, const BatchDev& D, hipStream_t st) {
-  kb_sweep<VAR, PREC, DEBUG><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
+  kb_sweep<VAR, PREC, DEBUG><<<D.nslots / swp_threads(VAR), swp_threads(VAR), 0, st>>>(A, D);
 }
 
 hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, bool debug, double* U, double* W,
@@ -981,7 +991,7 @@ hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, boo
     NCL_BSW(VAR_DO, 0) NCL_BSW(VAR_DO, 1) NCL_BSW(VAR_DO, 2)
 #undef NCL_BSW
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0);
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0, (uint32_t)swp_threads(D.variant));
   return hipGetLastError();
 }
 
@@ -1020,7 +1030,7 @@ hipError_t batch_fused(const SweepArgs& A, const BatchDev& D, const double* x, i
     if (D.variant == VAR_DO && precision == 2) e = fused_t<VAR_DO, 2>(A, D, x, fstate, order, blk_order, st);
     if (e != hipSuccess) return e;
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0);
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0, (uint32_t)SW_THREADS);
   return hipGetLastError();
 }
 
@@ -1097,7 +1107,7 @@ hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, int precision
     else if (precision == 2) kb_list_force<2><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
     else kb_list_force<1><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 1);
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 1, (uint32_t)SW_THREADS);
   return hipGetLastError();
 }
 

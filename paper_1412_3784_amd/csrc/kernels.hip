@@ -498,27 +498,28 @@ __global__ void __launch_bounds__(SW_THREADS) k_sweep_fallback(SweepArgs A, Cell
 }
 
 // one thread per particle in cell order, neighbour data straight from
-// global memory (L1/L2); partial sums per workgroup.  Four waves per SIMD
-// (at most 128 VGPRs; the 10-deep list of 16-byte entries, whose LDS the
-// block's reduction reuses, makes 40 KB, so four workgroups fill the CU's
-// 160 KB) hide more load latency than three: measured 0.80 -> 0.70 ms at
-// 1 M LJ.
+// global memory (L1/L2); partial sums per workgroup (swp_threads(VAR)
+// lanes).  Four waves per SIMD (at most 128 VGPRs; the 10-deep list of
+// 16-byte entries, whose LDS the block's reduction reuses, makes 160 bytes
+// per lane, so 16 waves fill the CU's 160 KB) hide more load latency than
+// three: measured 0.80 -> 0.70 ms at 1 M LJ.
 template <int VAR, int PREC, bool DEBUG>
-__global__ void __launch_bounds__(SW_THREADS, 4) k_sweep_particle(SweepArgs A, CellGeom g) {
-  __shared__ SweepSmem sm;
+__global__ void __launch_bounds__(swp_threads(VAR), 4) k_sweep_particle(SweepArgs A, CellGeom g) {
+  constexpr int BT = swp_threads(VAR);
+  __shared__ SweepSmemT<BT> sm;
   const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-  const uint32_t s = lb * SW_THREADS + threadIdx.x;
+  const uint32_t s = lb * BT + threadIdx.x;
   Acc<PREC, DEBUG> acc;
   uint32_t nbh = 0;
   if (s < A.n) {
-    PairList L(sm.plist + threadIdx.x);
+    PairListS<BT> L(sm.plist + threadIdx.x);
     sweep_particle<VAR, PREC, DEBUG>(A, g, s, acc, nbh, L);
     write_particle<VAR, PREC, DEBUG>(A, g, s, acc);
   }
   double v[7];
   acc_energy(acc, v);
   const uint32_t st4[4] = {acc.cand, acc.pairs, acc.fp64, nbh};
-  block_commit(A, lb, v, st4, sm.red);
+  block_commit<BT / 64>(A, lb, v, st4, sm.red);
 }
 
 // first level of the fixed-order reduction: block r sums partial slots
@@ -596,14 +597,15 @@ static void sweep_t(const SweepLaunch& L, hipStream_t st, uint32_t nslots) {
     k_sweep_tile<VAR, PREC, DEBUG><<<nslots, SW_THREADS, 0, st>>>(*L.args, *L.g);
     k_sweep_fallback<VAR, PREC, DEBUG><<<min(nslots, 1024u), SW_THREADS, 0, st>>>(*L.args, *L.g);
   } else {
-    k_sweep_particle<VAR, PREC, DEBUG><<<nslots, SW_THREADS, 0, st>>>(*L.args, *L.g);
+    k_sweep_particle<VAR, PREC, DEBUG><<<nslots, swp_threads(VAR), 0, st>>>(*L.args, *L.g);
   }
 }
 
 hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
   const uint32_t n = L.args->n;
-  const uint32_t nbrick = (L.mode == SWEEP_TILED) ? (uint32_t)L.args->nbx * L.args->nby * L.args->nbz
-                                                  : cdiv(n, SW_THREADS);
+  const uint32_t nbrick = (L.mode == SWEEP_TILED)  ? (uint32_t)L.args->nbx * L.args->nby * L.args->nbz
+                          : (L.mode == SWEEP_HALF) ? cdiv(n, SW_THREADS)
+                                                   : cdiv(n, swp_threads(L.g->variant));
   if (L.mode == SWEEP_HALF) {
     k_fill_u32<<<1, 64, 0, st>>>((uint32_t*)L.args->stats, 8, 0u);
     if (n > 0) {

@@ -69,6 +69,16 @@ struct BuildLaunch {
 
 enum { SWEEP_TILED = 0, SWEEP_PARTICLE = 1, SWEEP_AUTO = 2, SWEEP_HALF = 3 };
 
+// Workgroup size of the single-box per-particle sweep, by cell-list variant.
+// Dynamic offset: one wave, so that a wave's LDS is freed when it ends
+// rather than when the slowest of its workgroup's waves ends (measured at
+// 1 M LJ: 0.683 -> 0.639 ms; 16 M: 7.96 -> 7.73 ms); dynamic size keeps
+// four (1 M equal, 16 M 9.76 against 9.88 ms).  The sweep writes one
+// partial slot per workgroup, so a launch holds ceil(n / size) slots, at
+// most ceil(n / SWP_MIN_THREADS).
+constexpr int swp_threads(int variant) { return variant == VAR_DO ? 64 : 256; }
+constexpr int SWP_MIN_THREADS = 64;
+
 struct SweepLaunch {
   int mode;  // SWEEP_TILED, SWEEP_PARTICLE or SWEEP_HALF
   const CellGeom* g;

@@ -183,7 +183,7 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 }
 
 // Per-lane list of in-range pairs waiting for evaluation (LDS, entry e of
-// lane t at base[e * SW_THREADS + t]); evaluated by whole waves so that no
+// lane t at base[e * S + t] for a workgroup of S lanes); evaluated by whole waves so that no
 // lane runs the pair code alone.  An entry holds the separation in FP32 and
 // r^2 rounded once from the FP64 screening value: recomputing r^2 from the
 // three rounded components instead would add their rounding, which the WCA
@@ -200,16 +200,19 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 // met one (about 0.3 close pairs per particle in a uniform random liquid).
 constexpr int PL_K = 10;
 constexpr int SW_THREADS_P = 256;
-constexpr int PL_STRIDE = SW_THREADS_P;  // in entries
 typedef float pl_entry __attribute__((ext_vector_type(4)));      // (d_x, d_y, d_z, r^2)
 typedef __attribute__((address_space(3))) pl_entry lds_entry;  // 32-bit LDS pointer
-struct PairList {
+// S: lanes of the workgroup (the stride between a lane's entries)
+template <int S>
+struct PairListS {
+  static constexpr int stride = S;  // in entries
   lds_entry* base;
   lds_entry* q;    // next ordinary entry (growing up)
   lds_entry* top;  // last FP64-path entry (growing down from base + PL_K)
-  __device__ explicit PairList(pl_entry* p)
-      : base((lds_entry*)p), q((lds_entry*)p), top((lds_entry*)p + PL_K * PL_STRIDE) {}
+  __device__ explicit PairListS(pl_entry* p)
+      : base((lds_entry*)p), q((lds_entry*)p), top((lds_entry*)p + PL_K * S) {}
 };
+using PairList = PairListS<SW_THREADS_P>;
 
 // lattice image of a deferred pair, three 10-bit biased components
 __device__ inline uint32_t pack_image(const int* m) {
@@ -243,9 +246,9 @@ __device__ inline void exact_pair(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
 }
 
 // the lane's ordinary entries
-template <int PREC, bool DEBUG>
-__device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PairList& L) {
-  for (const lds_entry* e = L.base; e != L.q; e += PL_STRIDE) {
+template <int PREC, bool DEBUG, class PL>
+__device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PL& L) {
+  for (const lds_entry* e = L.base; e != L.q; e += PL::stride) {
     const pl_entry v = *e;
     pair32(acc, A.p32, A.p64, v.x, v.y, v.z, v.w, (double)v.w);
     acc.pairs += 1;
@@ -254,24 +257,24 @@ __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, Pai
 }
 
 // the lane's FP64-path entries
-template <int PREC, bool DEBUG>
+template <int PREC, bool DEBUG, class PL>
 __device__ inline void flush_exact(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
-                                   const int4& wi, PairList& L) {
-  const lds_entry* end = L.base + PL_K * PL_STRIDE;
-  for (const lds_entry* e = L.top; e != end; e += PL_STRIDE) {
+                                   const int4& wi, PL& L) {
+  const lds_entry* end = L.base + PL_K * PL::stride;
+  for (const lds_entry* e = L.top; e != end; e += PL::stride) {
     const pl_entry v = *e;
     exact_pair(acc, A, g, s, __float_as_uint(v.x), __float_as_uint(v.y), wi);
   }
-  L.top = L.base + PL_K * PL_STRIDE;
+  L.top = L.base + PL_K * PL::stride;
 }
 
 // room for the next group of four candidates in every lane's list
-template <int PREC, bool DEBUG>
+template <int PREC, bool DEBUG, class PL>
 __device__ inline void make_room(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
-                                 const int4& wi, PairList& L) {
-  if (__ballot(L.q + 4 * PL_STRIDE > L.top) != 0) {
+                                 const int4& wi, PL& L) {
+  if (__ballot(L.q + 4 * PL::stride > L.top) != 0) {
     flush_list(acc, A, L);
-    if (__ballot(L.q + 4 * PL_STRIDE > L.top) != 0) flush_exact(acc, A, g, s, wi, L);
+    if (__ballot(L.q + 4 * PL::stride > L.top) != 0) flush_exact(acc, A, g, s, wi, L);
   }
 }
 
@@ -284,10 +287,10 @@ __device__ inline void make_room(Acc<PREC, DEBUG>& acc, const SweepArgs& A, cons
 // of the dynamic-offset list, whose x step (w0, 0, 0) only changes d_x; dc
 // is then the centre offset of the row's x cell 0 and each candidate adds
 // ax_j w0, ax_j being its cell's x index (cell id - row base).
-template <int PREC, bool DEBUG, bool FLAT = false>
+template <int PREC, bool DEBUG, bool FLAT = false, class PL = PairList>
 __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, const CellGeom& g, uint32_t s,
                                   uint32_t cj, bool zero_image, const double* dc, const int* m,
-                                  const double* oi, const double4& pi64, const int4& wi, PairList& L,
+                                  const double* oi, const double4& pi64, const int4& wi, PL& L,
                                   uint32_t ncell = 1, uint32_t rowbase = 0) {
   const uint32_t st = A.cstart[A.cell0 + cj] + A.pad, en = A.cstart[A.cell0 + cj + ncell] + A.pad;
   const uint32_t self = zero_image ? s : 0xffffffffu;
@@ -345,11 +348,11 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: deferred
               // to the FP64 path (see flush_exact)
-              L.top -= PL_STRIDE;
+              L.top -= PL::stride;
               *L.top = pl_entry{__uint_as_float(j), __uint_as_float(pack_image(m)), 0.0f, 0.0f};
             } else {
               *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
-              L.q += PL_STRIDE;
+              L.q += PL::stride;
               debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
             }
           }
@@ -378,11 +381,11 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: deferred
               // to the FP64 path (see flush_exact)
-              L.top -= PL_STRIDE;
+              L.top -= PL::stride;
               *L.top = pl_entry{__uint_as_float(j), __uint_as_float(pack_image(m)), 0.0f, 0.0f};
             } else {
               *L.q = pl_entry{(float)dx, (float)dy, (float)dz, (float)r2};
-              L.q += PL_STRIDE;
+              L.q += PL::stride;
               debug_pair<DEBUG>(acc.dcount, acc.dhash, A, g, j, m, wi);
             }
           }
@@ -418,9 +421,9 @@ __device__ inline double warp_sum(double v) {
 // per-particle sweep straight from global memory (used for bricks whose
 // neighbourhood does not fit the LDS tile)
 // ---------------------------------------------------------------------------
-template <int VAR, int PREC, bool DEBUG, bool DIVFREE = false>
+template <int VAR, int PREC, bool DEBUG, bool DIVFREE = false, class PL = PairList>
 __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s, Acc<PREC, DEBUG>& acc,
-                               uint32_t& nbh, PairList& L) {
+                               uint32_t& nbh, PL& L) {
   const float4 pi = A.pos32[s];
   const double4 pi64 = A.pos64[s];
   const int4 wi = DEBUG ? A.wrap[s] : make_int4(0, 0, 0, 0);
@@ -554,9 +557,10 @@ __device__ inline void acc_energy(const Acc<PREC, DEBUG>& acc, double* v) {
 // -> partial[PART_STRIDE * slot], summed over slots by the finalisation.
 // (Statistics are not added atomically: one counter hit by every wave of a
 // launch serialises in one L2 channel and cost a quarter of the sweep.)
-// Every thread of the block must call it.  `red` is LDS for the four
+// Every thread of the block (NW waves) must call it.  `red` is LDS for the
 // waves' sums; it may alias memory the block has finished with (the pair
 // lists), since the block synchronises before writing it.
+template <int NW = 4>
 __device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const double* v, const uint32_t* st4,
                                     double (*red)[PART_STRIDE]) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -575,7 +579,9 @@ __device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const dou
   }
   __syncthreads();
   if (threadIdx.x < PART_STRIDE && threadIdx.x != 7) {
-    const double t = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    double t = red[0][threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) t += red[w][threadIdx.x];
     A.partial[PART_STRIDE * (size_t)slot + threadIdx.x] = t;
   }
 }
@@ -587,10 +593,12 @@ __device__ inline void block_commit(const SweepArgs& A, uint32_t slot, const dou
 
 // LDS of the per-particle sweeps: the per-lane pair lists, reused for the
 // block's reduction once every lane has flushed its list
-union SweepSmem {
-  pl_entry plist[PL_K * SW_THREADS_P];
-  double red[4][PART_STRIDE];
+template <int BT>
+union SweepSmemT {
+  pl_entry plist[PL_K * BT];
+  double red[BT / 64][PART_STRIDE];
 };
+using SweepSmem = SweepSmemT<SW_THREADS_P>;
 
 
 }  // namespace ncl
