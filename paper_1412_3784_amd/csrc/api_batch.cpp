@@ -298,7 +298,9 @@ int ncl_batch_create(ncl_batch_handle* out, int device, void* stream, int32_t nr
   if (e == hipSuccess) e = dalloc(&b->rs_vb, tot);
   if (e == hipSuccess) e = dalloc(&b->rs_hist, rs_offsets((uint32_t)tot));
   if (e == hipSuccess) e = dalloc(&b->rs_off, rs_offsets((uint32_t)tot));
-  if (e == hipSuccess) e = dalloc(&b->partial, PART_STRIDE * (slots / SWP_MIN_THREADS + 1));
+  // one partial per sweep workgroup, then (one-wave workgroups) their sums per
+  // 256-slot block
+  if (e == hipSuccess) e = dalloc(&b->partial, PART_STRIDE * (slots / SWP_MIN_THREADS + slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->kpart, 3 * (slots / 256 + 1));
   if (e == hipSuccess) e = dalloc(&b->pol, nrep);
   if (e == hipSuccess) e = dalloc(&b->t0_d, nrep);

@@ -420,26 +420,30 @@ __global__ void __launch_bounds__(SW_THREADS, 4) kb_fused(SweepArgs A0, BatchDev
   sweep_block<VAR, PREC, false>(A0, D, lb, sm.sw);
 }
 
+// partials of one-wave workgroups -> one partial per 256-slot block, the
+// four waves summed in the order a 256-lane workgroup sums them (so the
+// per-replica sums do not depend on the sweep's workgroup size)
+__global__ void kb_combine4(const double* __restrict__ in, uint32_t nblk, double* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nblk * PART_STRIDE) return;
+  const uint32_t b = i / PART_STRIDE, k = i % PART_STRIDE;
+  const double* p = in + 4 * PART_STRIDE * (size_t)b + k;
+  out[i] = ((p[0] + p[PART_STRIDE]) + p[2 * PART_STRIDE]) + p[3 * PART_STRIDE];
+}
+
 // per replica: U = 1/2 sum u, W = 1/2 sum w over its workgroups, in order;
 // DO rotates W back to Cartesian
 // cart: the partials are already Cartesian (neighbour-list forces), so the
 // dynamic-offset rotation back from the cell frame is skipped
 __global__ void kb_finalize(BatchDev D, const double* __restrict__ partial, double* __restrict__ U,
-                            double* __restrict__ W, unsigned long long* __restrict__ stats, int cart, uint32_t bt) {
+                            double* __restrict__ W, unsigned long long* __restrict__ stats, int cart) {
   __shared__ double red[4][PART_STRIDE];
   const uint32_t r = blockIdx.x;
-  // per 256-slot block: its bt-slot partials summed in the order a 256-lane
-  // workgroup sums its waves, so both block sizes give the same sums
-  const uint32_t b0 = D.slot_off[r] / 256, b1 = D.slot_off[r + 1] / 256, sub = 256 / bt;
+  const uint32_t b0 = D.slot_off[r] / 256, b1 = D.slot_off[r + 1] / 256;
   double v[PART_STRIDE] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (uint32_t b = b0 + threadIdx.x; b < b1; b += blockDim.x)
     for (int k = 0; k < PART_STRIDE; ++k)
-      if (k != 7) {
-        const double* pb = partial + PART_STRIDE * (size_t)b * sub + k;
-        double t = pb[0];
-        for (uint32_t q = 1; q < sub; ++q) t += pb[PART_STRIDE * q];
-        v[k] += t;
-      }
+      if (k != 7) v[k] += partial[PART_STRIDE * (size_t)b + k];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int k = 0; k < PART_STRIDE; ++k) {
     const double t = warp_sum(v[k]);
@@ -991,7 +995,15 @@ hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, boo
     NCL_BSW(VAR_DO, 0) NCL_BSW(VAR_DO, 1) NCL_BSW(VAR_DO, 2)
 #undef NCL_BSW
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0, (uint32_t)swp_threads(D.variant));
+  const double* part = A.partial;
+  if (swp_threads(D.variant) == 64 && D.nslots > 0) {
+    // the combined partials follow the one-wave ones (nslots / 64 slots)
+    double* comb = A.partial + PART_STRIDE * (size_t)(D.nslots / 64);
+    const uint32_t nblk = D.nslots / 256;
+    kb_combine4<<<cdivb((uint64_t)nblk * PART_STRIDE, 256), 256, 0, st>>>(A.partial, nblk, comb);
+    part = comb;
+  }
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, part, U, W, A.stats, 0);
   return hipGetLastError();
 }
 
@@ -1030,7 +1042,7 @@ hipError_t batch_fused(const SweepArgs& A, const BatchDev& D, const double* x, i
     if (D.variant == VAR_DO && precision == 2) e = fused_t<VAR_DO, 2>(A, D, x, fstate, order, blk_order, st);
     if (e != hipSuccess) return e;
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0, (uint32_t)SW_THREADS);
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 0);
   return hipGetLastError();
 }
 
@@ -1107,7 +1119,7 @@ hipError_t batch_list_force(const SweepArgs& A, const BatchDev& D, int precision
     else if (precision == 2) kb_list_force<2><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
     else kb_list_force<1><<<D.nslots / SW_THREADS, SW_THREADS, 0, st>>>(A, D);
   }
-  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 1, (uint32_t)SW_THREADS);
+  kb_finalize<<<D.nrep, 256, 0, st>>>(D, A.partial, U, W, A.stats, 1);
   return hipGetLastError();
 }
 
