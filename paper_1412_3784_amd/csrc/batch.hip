@@ -996,9 +996,10 @@ hipError_t batch_sweep(const SweepArgs& A, const BatchDev& D, int precision, boo
 #undef NCL_BSW
   }
   const double* part = A.partial;
-  if (swp_threads(D.variant) == 64 && D.nslots > 0) {
+  static_assert(256 / SWP_MIN_THREADS == 4, "kb_combine4 sums four one-wave partials");
+  if (swp_threads(D.variant) == SWP_MIN_THREADS && D.nslots > 0) {
     // the combined partials follow the one-wave ones (nslots / 64 slots)
-    double* comb = A.partial + PART_STRIDE * (size_t)(D.nslots / 64);
+    double* comb = A.partial + PART_STRIDE * (size_t)(D.nslots / SWP_MIN_THREADS);
     const uint32_t nblk = D.nslots / 256;
     kb_combine4<<<cdivb((uint64_t)nblk * PART_STRIDE, 256), 256, 0, st>>>(A.partial, nblk, comb);
     part = comb;

@@ -183,8 +183,8 @@ __device__ inline void debug_pair(int64_t& cnt, uint64_t& hsh, const SweepArgs& 
 }
 
 // Per-lane list of in-range pairs waiting for evaluation (LDS, entry e of
-// lane t at base[e * S + t] for a workgroup of S lanes); evaluated by whole waves so that no
-// lane runs the pair code alone.  An entry holds the separation in FP32 and
+// lane t at base[e * S + t] for a workgroup of S lanes); evaluated by whole
+// waves so that no lane runs the pair code alone.  An entry holds the separation in FP32 and
 // r^2 rounded once from the FP64 screening value: recomputing r^2 from the
 // three rounded components instead would add their rounding, which the WCA
 // force near its cut-off (|f'| about 75 eps/sigma^2 at r = 1.11 sigma)
