@@ -96,25 +96,23 @@ __global__ void kb_cell_index(BatchDev D, const double* __restrict__ x) {
   D.cell_of[i] = c;
 }
 
-// sorted position s (replica-major, cells in order) -> slot in the
-// replica's padded range: the sorted positions n_off[r] .. n_off[r + 1] - 1
-// hold replica r's particles, since every key lies in its replica's cell
-// range (an invalid replica's particles all in its cell 0)
-__global__ void kb_place(BatchDev D) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= D.n) return;
-  const uint32_t r = rep_of(D, s);
-  D.perm[s + (D.slot_off[r] - D.n_off[r])] = D.rs_va[s];
-}
-
 __global__ void kb_gather(BatchDev D, const double* __restrict__ x) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= D.nslots) return;
-  const uint32_t i = D.perm[s];
-  if (i == PAD_SLOT) return;
-  // a block's slots belong to one replica: its geometry is read through
-  // scalar loads
+  // a block's slots belong to one replica: its offsets and geometry are read
+  // through scalar loads.  Every key lies in its replica's cell range (an
+  // invalid replica's particles all in its cell 0), so the sorted positions
+  // n_off[r] .. n_off[r + 1] - 1 hold replica r's particles in cell order:
+  // slot s takes sorted position n_off[r] + (s - slot_off[r]); the slots past
+  // the replica's count are padding.
   const uint32_t r = __builtin_amdgcn_readfirstlane(D.blk_rep[s / SW_THREADS]);
+  const uint32_t q = s - D.slot_off[r];
+  if (q >= D.n_off[r + 1] - D.n_off[r]) {
+    D.perm[s] = PAD_SLOT;
+    return;
+  }
+  const uint32_t i = D.rs_va[D.n_off[r] + q];
+  D.perm[s] = i;
   const CellGeom& g = D.geom[r];
   const double p[3] = {x[3 * (size_t)i], x[3 * (size_t)i + 1], x[3 * (size_t)i + 2]};
   double xw[3];
@@ -678,7 +676,6 @@ hipError_t batch_prologue(const BatchDev& D, int off, double h, hipStream_t st) 
 }
 
 hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
-  kb_fill_u32<<<cdivb(D.nslots, 256), 256, 0, st>>>(D.perm, D.nslots, PAD_SLOT);
   if (D.n > 0) kb_cell_index<<<cdivb(D.n, 256), 256, 0, st>>>(D, x);
   const uint32_t* keys = D.cell_of;
   hipError_t e = radix_sort_cells(D.cell_of, D.rank, D.rs_va, D.rs_vb, D.n, D.ncells, D.rs_hist, D.rs_off,
@@ -688,10 +685,7 @@ hipError_t batch_build(const BatchDev& D, const double* x, hipStream_t st) {
   // launch of their own (measured faster here than inside kb_gather)
   if (e == hipSuccess) e = fill_empty_runs(D.cstart, D.ncells, st);
   if (e != hipSuccess) return e;
-  if (D.n > 0) {
-    kb_place<<<cdivb(D.n, 256), 256, 0, st>>>(D);
-    kb_gather<<<cdivb(D.nslots, 256), 256, 0, st>>>(D, x);
-  }
+  if (D.nslots > 0) kb_gather<<<cdivb(D.nslots, 256), 256, 0, st>>>(D, x);
   return hipGetLastError();
 }
 
