@@ -618,9 +618,10 @@ hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
     }
     return hipGetLastError();
   }
-  k_fill_u32<<<1, 64, 0, st>>>((uint32_t*)L.args->stats, 8, 0u);
-  k_fill_u32<<<1, 64, 0, st>>>(L.args->overflow, 1, 0u);
   if (n > 0 && nbrick > 0) {
+    // the finalisation writes every statistic; the overflow queue exists for
+    // the tiled sweep only
+    if (L.mode == SWEEP_TILED) k_fill_u32<<<1, 64, 0, st>>>(L.args->overflow, 1, 0u);
     const int var = L.g->variant, prec = L.precision;
     const bool dbg = L.debug;
 #define NCL_SW(V, P)                                      \
@@ -633,6 +634,7 @@ hipError_t launch_sweep(const SweepLaunch& L, hipStream_t st) {
 #undef NCL_SW
     finalize(L, st, nbrick, 0.5);
   } else {
+    k_fill_u32<<<1, 64, 0, st>>>((uint32_t*)L.args->stats, 8, 0u);
     k_zero_f64<<<1, 64, 0, st>>>(L.U, 1);
     k_zero_f64<<<1, 64, 0, st>>>(L.W, 9);
   }
