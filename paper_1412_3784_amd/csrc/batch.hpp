@@ -15,9 +15,9 @@ struct BatchDev {
   double rc;
   double rc_cells;           // cut-off the cells are built for: rc, or rc + skin with neighbour lists
   const uint32_t* n_off;     // [nrep+1] particles, input order
-  const uint32_t* slot_off;  // [nrep+1] slots (multiples of the workgroup)
+  const uint32_t* slot_off;  // [nrep+1] slots (multiples of 256)
   const uint32_t* cell_off;  // [nrep+1] cell capacity offsets
-  const uint32_t* blk_rep;   // [nslots / 256] replica of each sweep workgroup
+  const uint32_t* blk_rep;   // [nslots / 256] replica of each 256-slot block
   const uint32_t* in_rep;    // [ceil(n / 256)] replica of particle 256 b (input and sorted order alike)
   const RemapPolicy* pol;    // [nrep]
   const double* t0;          // [nrep] strain time at step 0
