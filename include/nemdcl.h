@@ -65,7 +65,10 @@ extern "C" {
  *              equals the FP64 one; pairs closer than a close-pair radius
  *              take their separation and pair terms in FP64 (the force is
  *              then added to the FP32 sums, the energy to an FP64 sum).
- * FP32_KAHAN:  as FP32, with Kahan-compensated per-particle sums.            */
+ * FP32_KAHAN:  as FP32, with Kahan-compensated per-particle force sums (the
+ *              per-particle sweep compensates once per evaluation round of
+ *              at most ten pairs summed in FP32, the other schedules once
+ *              per pair).                                                   */
 #define NCL_PREC_FP64 0
 #define NCL_PREC_FP32 1
 #define NCL_PREC_FP32_KAHAN 2

@@ -137,23 +137,18 @@ __device__ inline double phi64(const Pot64& p, double r2, float r2i) {
 
 // one FP32 pair: force and virial in FP32 from the FP32 separation and r2
 // (r^2 rounded once from an FP64 value), energy in FP64 from r2e, the FP64
-// r^2 where the caller has it (else r2 widened)
+// r^2 where the caller has it (else r2 widened); the force is added to
+// (bx, by, bz) in FP32
 template <int PREC, bool DEBUG>
-__device__ inline void pair32(Acc<PREC, DEBUG>& acc, const Pot32& p, const Pot64& p64, float dx, float dy, float dz,
-                              float r2, double r2e) {
+__device__ inline void pair32_to(Acc<PREC, DEBUG>& acc, const Pot32& p, const Pot64& p64, float dx, float dy,
+                                 float dz, float r2, double r2e, float& bx, float& by, float& bz) {
   const float r2i = __builtin_amdgcn_rcpf(r2);
   const float s2 = p.sig2 * r2i;
   const float s6 = s2 * s2 * s2;
   const float fs = r2i * s6 * fmaf(p.eps48, s6, -p.eps24);
-  if (PREC == 2) {
-    kahan_add(acc.fx, acc.kx, -fs * dx);
-    kahan_add(acc.fy, acc.ky, -fs * dy);
-    kahan_add(acc.fz, acc.kz, -fs * dz);
-  } else {
-    acc.fx = fmaf(-fs, dx, acc.fx);
-    acc.fy = fmaf(-fs, dy, acc.fy);
-    acc.fz = fmaf(-fs, dz, acc.fz);
-  }
+  bx = fmaf(-fs, dx, bx);
+  by = fmaf(-fs, dy, by);
+  bz = fmaf(-fs, dz, bz);
   acc.gu += phi64(p64, r2e, r2i);
   const float fdx = fs * dx, fdy = fs * dy;
   acc.w[0] = fmaf(fdx, dx, acc.w[0]);
@@ -162,6 +157,21 @@ __device__ inline void pair32(Acc<PREC, DEBUG>& acc, const Pot32& p, const Pot64
   acc.w[3] = fmaf(fdx, dy, acc.w[3]);
   acc.w[4] = fmaf(fdx, dz, acc.w[4]);
   acc.w[5] = fmaf(fdy, dz, acc.w[5]);
+}
+
+// one FP32 pair into the particle's sums (Kahan mode: compensated)
+template <int PREC, bool DEBUG>
+__device__ inline void pair32(Acc<PREC, DEBUG>& acc, const Pot32& p, const Pot64& p64, float dx, float dy, float dz,
+                              float r2, double r2e) {
+  if (PREC == 2) {
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    pair32_to(acc, p, p64, dx, dy, dz, r2, r2e, bx, by, bz);
+    kahan_add(acc.fx, acc.kx, bx);
+    kahan_add(acc.fy, acc.ky, by);
+    kahan_add(acc.fz, acc.kz, bz);
+  } else {
+    pair32_to(acc, p, p64, dx, dy, dz, r2, r2e, acc.fx, acc.fy, acc.fz);
+  }
 }
 
 template <bool DEBUG>
@@ -245,13 +255,26 @@ __device__ inline void exact_pair(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
   }
 }
 
-// the lane's ordinary entries
+// the lane's ordinary entries (Kahan mode: the round's forces, at most PL_K
+// pairs, are summed in FP32 and join the compensated sums once per round)
 template <int PREC, bool DEBUG, class PL>
 __device__ inline void flush_list(Acc<PREC, DEBUG>& acc, const SweepArgs& A, PL& L) {
-  for (const lds_entry* e = L.base; e != L.q; e += PL::stride) {
-    const pl_entry v = *e;
-    pair32(acc, A.p32, A.p64, v.x, v.y, v.z, v.w, (double)v.w);
-    acc.pairs += 1;
+  if constexpr (PREC == 2) {
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    for (const lds_entry* e = L.base; e != L.q; e += PL::stride) {
+      const pl_entry v = *e;
+      pair32_to(acc, A.p32, A.p64, v.x, v.y, v.z, v.w, (double)v.w, bx, by, bz);
+      acc.pairs += 1;
+    }
+    kahan_add(acc.fx, acc.kx, bx);
+    kahan_add(acc.fy, acc.ky, by);
+    kahan_add(acc.fz, acc.kz, bz);
+  } else {
+    for (const lds_entry* e = L.base; e != L.q; e += PL::stride) {
+      const pl_entry v = *e;
+      pair32(acc, A.p32, A.p64, v.x, v.y, v.z, v.w, (double)v.w);
+      acc.pairs += 1;
+    }
   }
   L.q = L.base;
 }
