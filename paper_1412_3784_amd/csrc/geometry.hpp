@@ -468,7 +468,10 @@ NCL_HD void cell_geom_bands(CellGeom* g, double rc) {
     for (int c = 0; c < 3; ++c) s += 0.5 * fabs(g->cen[3 * r + c]);
     omax = fmax(omax, s);
   }
-  const double od = 0.5 * ulp32(omax) * 1.7320508075688772;
+  // dynamic offset: plus the FP64 rounding of a home x placed relative to the
+  // first cell of the id numbering (at most ncells w0 + 8 rc from it)
+  const double big = (double)g->nc[0] * g->nc[1] * g->nc[2] * g->w[0] + 8.0 * rc;
+  const double od = 0.5 * ulp32(omax) * 1.7320508075688772 + (g->variant == VAR_DO ? ldexp(big, -52) : 0.0);
   const double er = 2.0 * rc * od + od * od + 1e-15 * rc * rc;
   g->rc2_lo64 = rc * rc - 4.0 * er;
   g->rc2_hi64 = rc * rc + 4.0 * er;

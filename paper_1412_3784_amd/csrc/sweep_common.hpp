@@ -344,6 +344,11 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
     // candidates' FP32 offsets are widened to FP64, so the separation is
     // exact up to the rounding of the stored FP32 offsets
     const double xo = oi[0] - dc[0], yo = oi[1] - dc[1], zo = oi[2] - dc[2];
+    // FLAT runs: the home x relative to the centre of x cell 0 of the cell
+    // id numbering, so that a candidate's cell id times w0 gives its cell's
+    // centre directly (rounding of this sum at most 2^-53 of ncells w0, kept
+    // inside the screen's band)
+    const double xo2 = FLAT ? xo + (double)rowbase * g.w[0] : 0.0;
     // four candidate loads in flight per step from one address; entries
     // past the run (up to three; the array has four spare entries at its
     // end) are read and masked out
@@ -363,8 +368,9 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t j = j0 + u;
-          double dx = (double)pj[u].x - xo;
-          if (FLAT) dx = fma((double)(int32_t)(__float_as_uint(pj[u].w) - rowbase), g.w[0], dx);
+          // FLAT: x-cell index times w0 from the cell id (xo2 = xo + rowbase w0)
+          const double dx = FLAT ? fma((double)__float_as_uint(pj[u].w), g.w[0], -xo2) + (double)pj[u].x
+                                 : (double)pj[u].x - xo;
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           if (r2 < g.rc2_hi64 && j < en && (!CHECK_SELF || j != self)) {
@@ -396,8 +402,9 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t j = j0 + u;
-          double dx = (double)pj[u].x - xo;
-          if (FLAT) dx = fma((double)(int32_t)(__float_as_uint(pj[u].w) - rowbase), g.w[0], dx);
+          // FLAT: x-cell index times w0 from the cell id (xo2 = xo + rowbase w0)
+          const double dx = FLAT ? fma((double)__float_as_uint(pj[u].w), g.w[0], -xo2) + (double)pj[u].x
+                                 : (double)pj[u].x - xo;
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           if (r2 < g.rc2_hi64 && j < en && j != self) {
