@@ -349,6 +349,11 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
     // centre directly (rounding of this sum at most 2^-53 of ncells w0, kept
     // inside the screen's band)
     const double xo2 = FLAT ? xo + (double)rowbase * g.w[0] : 0.0;
+    // run-end and self tests of candidate j0 + u against bounds shifted by u
+    // (signed: slots are below 2^31, and en - u may be negative; j0 < en holds
+    // inside the loop)
+    const int32_t enu[4] = {(int32_t)en, (int32_t)en - 1, (int32_t)en - 2, (int32_t)en - 3};
+    const uint32_t selfu[4] = {self, self - 1u, self - 2u, self - 3u};
     // four candidate loads in flight per step from one address; entries
     // past the run (up to three; the array has four spare entries at its
     // end) are read and masked out
@@ -373,7 +378,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                                  : (double)pj[u].x - xo;
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          if (r2 < g.rc2_hi64 && j < en && (!CHECK_SELF || j != self)) {
+          if (r2 < g.rc2_hi64 && (u == 0 || (int32_t)j0 < enu[u]) && (!CHECK_SELF || j0 != selfu[u])) {
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: deferred
               // to the FP64 path (see flush_exact)
@@ -407,7 +412,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                                  : (double)pj[u].x - xo;
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          if (r2 < g.rc2_hi64 && j < en && j != self) {
+          if (r2 < g.rc2_hi64 && (u == 0 || (int32_t)j0 < enu[u]) && j0 != selfu[u]) {
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: deferred
               // to the FP64 path (see flush_exact)
