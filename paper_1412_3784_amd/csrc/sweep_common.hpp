@@ -350,9 +350,9 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
     // inside the screen's band)
     const double xo2 = FLAT ? xo + (double)rowbase * g.w[0] : 0.0;
     // run-end and self tests of candidate j0 + u against bounds shifted by u
-    // (signed: slots are below 2^31, and en - u may be negative; j0 < en holds
-    // inside the loop)
-    const int32_t enu[4] = {(int32_t)en, (int32_t)en - 1, (int32_t)en - 2, (int32_t)en - 3};
+    // (en - u saturated at 0: no slot precedes it then; j0 < en holds inside
+    // the loop)
+    const uint32_t enu[4] = {en, en > 1u ? en - 1u : 0u, en > 2u ? en - 2u : 0u, en > 3u ? en - 3u : 0u};
     const uint32_t selfu[4] = {self, self - 1u, self - 2u, self - 3u};
     // four candidate loads in flight per step from one address; entries
     // past the run (up to three; the array has four spare entries at its
@@ -378,7 +378,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                                  : (double)pj[u].x - xo;
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          if (r2 < g.rc2_hi64 && (u == 0 || (int32_t)j0 < enu[u]) && (!CHECK_SELF || j0 != selfu[u])) {
+          if (r2 < g.rc2_hi64 && (u == 0 || j0 < enu[u]) && (!CHECK_SELF || j0 != selfu[u])) {
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: deferred
               // to the FP64 path (see flush_exact)
@@ -412,7 +412,7 @@ __device__ inline void visit_cell(Acc<PREC, DEBUG>& acc, const SweepArgs& A, con
                                  : (double)pj[u].x - xo;
           const double dy = (double)pj[u].y - yo, dz = (double)pj[u].z - zo;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          if (r2 < g.rc2_hi64 && (u == 0 || (int32_t)j0 < enu[u]) && j0 != selfu[u]) {
+          if (r2 < g.rc2_hi64 && (u == 0 || j0 < enu[u]) && j0 != selfu[u]) {
             if (r2 > g.rc2_lo64 || r2 < A.rclose2_64) {
               // within the rounding band of d_cut, or a close pair: deferred
               // to the FP64 path (see flush_exact)
