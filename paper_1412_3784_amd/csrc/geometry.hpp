@@ -72,6 +72,12 @@ NCL_HD int idiv_floor32(int a, int b) {  // b > 0
 }
 // floor(a / b), b > 0, by two comparisons when -b <= a < 2b (a cell index
 // plus or minus a few cells), else by a division
+// floor(a / b) for b > 0 from inv_b = 1 / b rounded to FP64: the product
+// (a + 1/2) inv_b is within a relative 2^-52 of (a + 1/2) / b, i.e. within
+// |a + 1/2| 2^-52 / b < 1 / (2 b) of it for |a| < 2^51, while (a + 1/2) / b
+// lies at least 1 / (2 b) from every integer; its floor is floor(a / b)
+NCL_HD int idiv_floor_f(int a, double inv_b) { return (int)floor(((double)a + 0.5) * inv_b); }
+
 NCL_HD int idiv_floor_near(int a, int b) {
   if (a >= -b && a < 2 * b) return (int)(a >= b) - (int)(a < 0);
   return idiv_floor32(a, b);
@@ -348,6 +354,7 @@ struct CellGeom {
   double ds_delta[27][3];  // DS: Lred diag(1/c) delta for the 27 stencil offsets
   double w[3];      // DO cell widths r_ii / l_i; DS: 1/c_i (fractional cell size)
   double inv_w[2];  // DO: 1 / w[0], 1 / w[1]
+  double inv_nc[3]; // 1 / nc[i] (idiv_floor_f)
   double grow[2];   // DO: neighbourhood growth (in cells) along x and y
   double rc2_lo64, rc2_hi64;  // per-particle screen: rc^2 minus / plus its rounding band
   int32_t nc[3];    // cells per axis (c_i or l_i)
@@ -444,6 +451,7 @@ NCL_HD int cell_geom_init(CellGeom* g, const double* Lred, const int64_t* Mtot, 
     g->grow[1] = do_tight ? rc / g->w[1] : 1.0;
     for (int q = 0; q < 27; ++q) g->ds_delta[q][0] = g->ds_delta[q][1] = g->ds_delta[q][2] = 0.0;
   }
+  for (int i = 0; i < 3; ++i) g->inv_nc[i] = 1.0 / (double)g->nc[i];
   return GEOM_OK;
 }
 

@@ -491,23 +491,24 @@ __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s
         }
   } else {
     // rectangular cells of the rotated box; layer k (z) is offset by
-    // k r23 in y, row (j, k) by j r12 + k r13 in x.  DIVFREE: the image
-    // indices by comparisons and the shifts in cells by the reciprocal
-    // widths (a cell only touched at the range's edge may then be visited
-    // or not; it holds no pair in range); otherwise by divisions.  Which is
-    // faster depends on the kernel's register allocation (measured: the
-    // batched sweep gains 5 %, the single-box sweep loses 27 % to spilled
-    // scalar registers).
+    // k r23 in y, row (j, k) by j r12 + k r13 in x.  The row and x image
+    // indices are exact floor divisions by the FP64 reciprocal cell counts
+    // (idiv_floor_f).  DIVFREE: the layer image by comparisons and the
+    // shifts in cells by the reciprocal widths (a cell only touched at the
+    // range's edge may then be visited or not; it holds no pair in range);
+    // otherwise by an FP64 division.  Which is faster depends on the
+    // kernel's register allocation (measured: the batched sweep gains 5 %,
+    // the single-box sweep loses to spilled scalar registers).
     const double w0 = g.w[0], w1 = g.w[1], w2 = g.w[2];
     for (int dz = -1; dz <= 1; ++dz) {
       const int C = c + dz;  // in [-1, nc[2]]
-      const int k = DIVFREE ? (int)(C >= g.nc[2]) - (int)(C < 0) : idiv_floor32(C, g.nc[2]);
+      const int k = DIVFREE ? (int)(C >= g.nc[2]) - (int)(C < 0) : idiv_floor_f(C, g.inv_nc[2]);
       const int cz = C - k * g.nc[2];
       const double fy = DIVFREE ? -(double)k * g.B[5] * g.inv_w[1] : -(double)k * g.B[5] / w1;
       const int B0 = (int)floor(b - g.grow[1] + fy);
       const int B1 = (int)ceil(b + 1 + g.grow[1] + fy) - 1;
       for (int Bq = B0; Bq <= B1; ++Bq) {
-        const int j = DIVFREE ? idiv_floor_near(Bq, g.nc[1]) : idiv_floor32(Bq, g.nc[1]);
+        const int j = idiv_floor_f(Bq, g.inv_nc[1]);
         const int by = Bq - j * g.nc[1];
         const double xs = (double)j * g.B[1] + (double)k * g.B[2];
         const double fx = DIVFREE ? -xs * g.inv_w[0] : -xs / w0;
@@ -515,8 +516,8 @@ __device__ void sweep_particle(const SweepArgs& A, const CellGeom& g, uint32_t s
         const int A1 = (int)ceil(a + 1 + g.grow[0] + fx) - 1;
         const uint32_t rowbase = (uint32_t)g.nc[0] * ((uint32_t)by + (uint32_t)g.nc[1] * (uint32_t)cz);
         // the row's cells A0..A1, one contiguous run per x image i
-        const int i0 = DIVFREE ? idiv_floor_near(A0, g.nc[0]) : idiv_floor32(A0, g.nc[0]);
-        const int i1 = DIVFREE ? idiv_floor_near(A1, g.nc[0]) : idiv_floor32(A1, g.nc[0]);
+        const int i0 = idiv_floor_f(A0, g.inv_nc[0]);
+        const int i1 = idiv_floor_f(A1, g.inv_nc[0]);
         for (int i = i0; i <= i1; ++i) {
           const int axlo = max(A0 - i * g.nc[0], 0), axhi = min(A1 - i * g.nc[0], g.nc[0] - 1);
           const int m[3] = {i, j, k};
