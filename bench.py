@@ -74,7 +74,7 @@ BUILD_DESIGN_BYTES_PER_PARTICLE = 140
 # scaled by the reading of the same counter for a plain 1 GiB elementwise
 # kernel in the same run; see profiles/sweep_particle_do_lj1M_traffic.md.
 # Valid only while the sweep sources hash to src_sha (null otherwise).
-SWEEP_TRAFFIC = {"bytes_per_launch": 130085090, "src_sha": "b57653597e4f0fe3"}
+SWEEP_TRAFFIC = {"bytes_per_launch": 130033571, "src_sha": "7dffc170a59caa23"}
 SWEEP_SOURCES = ["paper_1412_3784_amd/csrc/sweep_common.hpp", "paper_1412_3784_amd/csrc/kernels.hip",
                  "paper_1412_3784_amd/csrc/kernels.hpp", "paper_1412_3784_amd/csrc/geometry.hpp"]
 
