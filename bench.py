@@ -107,6 +107,8 @@ def parse():
     p.add_argument("--no-nemd", action="store_true", help="plain: skip the SLLOD leg")
     p.add_argument("--no-variants", action="store_true", help="plain: skip the other cell-list variant")
     p.add_argument("--nemd-steps", type=int, default=1000, help="plain: SLLOD steps of the nemd leg")
+    p.add_argument("--nemd-traj", type=int, default=4,
+                   help="plain: smallest replicas given their own 100-step FP64 oracle trajectory")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-copy-probe", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=3, help="oracle evaluations in the CPU baseline")
@@ -473,16 +475,16 @@ def energy_drift(hist, boxes, h):
     return np.abs(H - H[0] + work).max(axis=0) / np.abs(H[0])
 
 
-def nemd_measure(a, nsteps=1000, chunk=100, nshadow=4, traj_steps=100, skin=0.0):
+def nemd_measure(a, nsteps=1000, chunk=100, nshadow=4, traj_steps=100, skin=0.0, ntraj=4):
     """SLLOD run of the 64-replica LJ batch: nsteps steps in graph-replayed
     chunks of `chunk` steps (the time of each chunk's call is summed).  The
     oracle evaluates the forces of the `nshadow` smallest replicas on the
     GPU's own FP64 states at step 0 and after every chunk (shadow mode), and
     their pressure tensors P = (sum p p^T / m + W) / V are compared; the
-    smallest replica also runs its own FP64 oracle trajectory for
-    traj_steps steps, compared pointwise at its end and as time averages of
-    the diagonal pressure over the steps.  Returns the result dict and the
-    boxes."""
+    `ntraj` smallest replicas also run their own FP64 oracle trajectories
+    for traj_steps steps, compared pointwise at their end and as time
+    averages of the diagonal pressure over the steps.  Returns the result
+    dict and the boxes."""
     import torch
     import oracle
     from paper_1412_3784_amd import Batch
@@ -498,8 +500,8 @@ def nemd_measure(a, nsteps=1000, chunk=100, nshadow=4, traj_steps=100, skin=0.0)
     ps = [wl.maxwell_momenta(n_, 1.0, seed=5000 + r) for r, n_ in enumerate(ns)]
     order = [int(r) for r in np.argsort(ns, kind="stable")]
     shadow = order[:nshadow] if nshadow > 0 else []
-    r0 = order[0]
-    x0, p0 = xs[r0].copy(), ps[r0].copy()
+    trajr = order[:ntraj] if traj_steps > 0 else []
+    start = {r: (xs[r].copy(), ps[r].copy()) for r in trajr}
     x = torch.from_numpy(np.concatenate(xs)).to(dev)
     p = torch.from_numpy(np.concatenate(ps)).to(dev)
     del xs, ps
@@ -534,7 +536,7 @@ def nemd_measure(a, nsteps=1000, chunk=100, nshadow=4, traj_steps=100, skin=0.0)
     if shadow:
         shadow_check(0, W)
     hists, wall, done = [], 0.0, 0
-    traj_cmp = None
+    traj_cmp = {}
     while done < nsteps:
         k = min(chunk, nsteps - done)
         torch.cuda.synchronize()
@@ -548,8 +550,9 @@ def nemd_measure(a, nsteps=1000, chunk=100, nshadow=4, traj_steps=100, skin=0.0)
         if shadow:
             shadow_check(done, W)
         if done == traj_steps and traj_steps > 0:
-            sl = slice(off[r0], off[r0 + 1])
-            traj_cmp = (x[sl].cpu().numpy(), p[sl].cpu().numpy())
+            for r in trajr:
+                sl = slice(off[r], off[r + 1])
+                traj_cmp[r] = (x[sl].cpu().numpy(), p[sl].cpu().numpy())
     st = bt.stats()
     bt.close()
     hist = np.concatenate(hists)                  # (nsteps + 1, R, 8)
@@ -569,28 +572,41 @@ def nemd_measure(a, nsteps=1000, chunk=100, nshadow=4, traj_steps=100, skin=0.0)
             "median_rel_err": float(np.median([e["rel_err"] for e in perr])),
             "definition": "max_ab |P_gpu - P_oracle| / max_ab |P_oracle|, P = (sum p p^T / m + W) / V, "
                           "oracle forces on the GPU's FP64 state"}
-    if traj_cmp is not None:
-        b = boxes[r0]
+    trajs = []
+    for r in trajr:
+        if r not in traj_cmp:
+            continue
+        b = boxes[r]
+        x0, p0 = start[r]
         t1 = time.perf_counter()
         xo, po, ho = oracle.sllod(x0, p0, b.L0, b.A, b.t, b.automorphisms, b.pot, h, mass, traj_steps)
         t_or = time.perf_counter() - t1
         L = oracle.lattice_at(b.L0, b.A, b.t + traj_steps * h)
-        d = traj_cmp[0] - xo
+        d = traj_cmp[r][0] - xo
         d -= np.round(np.linalg.solve(L, d.T)).T @ L.T    # nearest image
         V = abs(np.linalg.det(b.L0))
-        hg = hist[:traj_steps + 1, r0]
+        hg = hist[:traj_steps + 1, r]
         pdiag_g = (hg[:, 2:5] + hg[:, 5:8]) / V
         pdiag_o = (ho[:, 2:5] + ho[:, 5:8]) / V
-        res["oracle_trajectory"] = {
-            "replica": r0, "n": ns[r0], "steps": traj_steps, "oracle_seconds": t_or,
+        trajs.append({
+            "replica": r, "n": ns[r], "steps": traj_steps, "oracle_seconds": t_or,
             "max_abs_dx_sigma": float(np.abs(d).max()),
-            "max_rel_dp": float(np.abs(traj_cmp[1] - po).max() / np.abs(po).max()),
+            "max_rel_dp": float(np.abs(traj_cmp[r][1] - po).max() / np.abs(po).max()),
             "time_avg_pressure_diag_gpu": pdiag_g.mean(axis=0).tolist(),
             "time_avg_pressure_diag_oracle": pdiag_o.mean(axis=0).tolist(),
             "time_avg_pressure_rel_diff": float(np.abs(pdiag_g.mean(0) - pdiag_o.mean(0)).max()
                                                 / np.abs(pdiag_o.mean(0)).max()),
             "energy_balance_rel_drift_oracle": float(np.abs(oracle.energy_balance(ho, b.A)).max()
-                                                     / abs(0.5 * ho[0, 5:8].sum() + ho[0, 1]))}
+                                                     / abs(0.5 * ho[0, 5:8].sum() + ho[0, 1]))})
+    if trajs:
+        # the smallest replica in full, then the worst figures over all
+        res["oracle_trajectory"] = trajs[0]
+        res["oracle_trajectories"] = {
+            "replicas": [t["replica"] for t in trajs], "n": [t["n"] for t in trajs], "steps": traj_steps,
+            "oracle_seconds": sum(t["oracle_seconds"] for t in trajs),
+            "max_abs_dx_sigma": max(t["max_abs_dx_sigma"] for t in trajs),
+            "max_rel_dp": max(t["max_rel_dp"] for t in trajs),
+            "max_time_avg_pressure_rel_diff": max(t["time_avg_pressure_rel_diff"] for t in trajs)}
     del x, p
     torch.cuda.empty_cache()
     return res, boxes
@@ -724,7 +740,7 @@ def main():
         if not a.no_nemd:
             log("nemd leg")
             gc.collect()
-            r, _ = nemd_measure(a, nsteps=a.nemd_steps)
+            r, _ = nemd_measure(a, nsteps=a.nemd_steps, ntraj=a.nemd_traj)
             out["nemd"] = r
     elif a.workload == "batch":
         boxes = run_batch(a, out)
