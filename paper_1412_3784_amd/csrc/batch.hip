@@ -562,35 +562,63 @@ __global__ void kb_drift(BatchDev D, double* __restrict__ x, const double* __res
 // lattice the prologue set for step n.  The arithmetic is that of a second
 // kick, a first kick and a drift in that order, so the trajectory does not
 // depend on the fusion; it reads x, p and F once and writes x and p once.
+// A workgroup's valid slots are a prefix of it and map to consecutive input
+// particles, so their coordinates are moved between HBM and LDS as three
+// contiguous runs of 8-byte words (a wave's access covers 512 contiguous
+// bytes, not every third word of 1.5 KB).
 template <typename FT>
 __global__ void kb_kick_drift(BatchDev D, double* __restrict__ x, double* __restrict__ p, const FT* __restrict__ F,
                               double h, double mass, int kick2) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t t = threadIdx.x;
   const uint32_t r = D.blk_rep[blockIdx.x];
-  const uint32_t i = padded_input(D, s, r);
-  __shared__ double ek[3], ez[3], hphi[3];
+  // slots q0 .. q0 + nv - 1 of replica r are its input particles n_off[r] + q
+  const uint32_t q0 = blockIdx.x * SW_THREADS - D.slot_off[r], nr = D.n_off[r + 1] - D.n_off[r];
+  const uint32_t nv = q0 < nr ? min(nr - q0, (uint32_t)SW_THREADS) : 0u;
+  const size_t b0 = 3 * ((size_t)D.n_off[r] + q0);
+  __shared__ double sx[3 * SW_THREADS], sp[3 * SW_THREADS];
+  __shared__ FT sf[3 * SW_THREADS];
+  for (uint32_t k = t; k < 3 * nv; k += SW_THREADS) {
+    sx[k] = x[b0 + k];
+    sp[k] = p[b0 + k];
+    sf[k] = F[b0 + k];
+  }
+  __shared__ double ek[3], ez[3], hphi[3], Ls[9], Lis[9];
   if (threadIdx.x < 3) ek[threadIdx.x] = exp(-0.5 * h * D.adiag[3 * (size_t)r + threadIdx.x]);
-  drift_factors(D, r, h, ez, hphi);  // synchronises the workgroup
+  // the replica's reduced basis and its inverse, once per workgroup (by the
+  // second wave, beside the first wave's factors)
+  static_assert(SW_THREADS > 64, "the basis is inverted by the second wave");
+  if (threadIdx.x == 64) {
+    double L[9], Li[9];
+    for (int k = 0; k < 9; ++k) L[k] = D.lred[9 * (size_t)r + k];
+    mat_inv(L, Li);
+    for (int k = 0; k < 9; ++k) {
+      Ls[k] = L[k];
+      Lis[k] = Li[k];
+    }
+  }
+  drift_factors(D, r, h, ez, hphi);  // synchronises the workgroup (the staged runs too)
   double k2[3] = {0.0, 0.0, 0.0};
-  if (i != PAD_SLOT) {
+  if (t < nv) {
     double v[3], q[3];
     for (int d = 0; d < 3; ++d) {
-      const double f = (double)F[3 * (size_t)i + d];
-      v[d] = p[3 * (size_t)i + d];
+      const double f = (double)sf[3 * t + d];
+      v[d] = sp[3 * t + d];
       if (kick2) {
         v[d] = (v[d] + 0.5 * h * f) * ek[d];
         k2[d] = v[d] * v[d] / mass;
       }
       v[d] = v[d] * ek[d] + 0.5 * h * f;
-      p[3 * (size_t)i + d] = v[d];
+      sp[3 * t + d] = v[d];
     }
-    for (int d = 0; d < 3; ++d) q[d] = ez[d] * x[3 * (size_t)i + d] + hphi[d] * v[d] / mass;
-    double Linv[9], L[9];
-    for (int k = 0; k < 9; ++k) L[k] = D.lred[9 * (size_t)r + k];
-    mat_inv(L, Linv);
+    for (int d = 0; d < 3; ++d) q[d] = ez[d] * sx[3 * t + d] + hphi[d] * v[d] / mass;
     double n[3];
-    for (int d = 0; d < 3; ++d) n[d] = floor(Linv[3 * d] * q[0] + Linv[3 * d + 1] * q[1] + Linv[3 * d + 2] * q[2]);
-    for (int d = 0; d < 3; ++d) x[3 * (size_t)i + d] = q[d] - (L[3 * d] * n[0] + L[3 * d + 1] * n[1] + L[3 * d + 2] * n[2]);
+    for (int d = 0; d < 3; ++d) n[d] = floor(Lis[3 * d] * q[0] + Lis[3 * d + 1] * q[1] + Lis[3 * d + 2] * q[2]);
+    for (int d = 0; d < 3; ++d) sx[3 * t + d] = q[d] - (Ls[3 * d] * n[0] + Ls[3 * d + 1] * n[1] + Ls[3 * d + 2] * n[2]);
+  }
+  __syncthreads();
+  for (uint32_t k = t; k < 3 * nv; k += SW_THREADS) {
+    x[b0 + k] = sx[k];
+    p[b0 + k] = sp[k];
   }
   if (kick2) {
     __shared__ double red[4][4];
