@@ -132,13 +132,16 @@ def copy_probe():
     del x, y
 
 
-def roofline_alu(tot_cands, tot_evals, t_force, steps, kernel, n):
+def roofline_alu(tot_cands, tot_evals, t_force, steps, kernel, n, measured=False):
     """the sweep against the VALU: algorithmic lane-ops (7 per candidate, 40
-    per pair evaluation) over the force call's event time"""
+    per pair evaluation) over the force call's event time.  `measured`: the
+    launch is the one SWEEP_TRAFFIC was counted on (1 M LJ, dynamic offset,
+    FP32, per-particle sweep); other launches report no traffic."""
     ops = OPS_PER_CANDIDATE * tot_cands + OPS_PER_PAIR * tot_evals
     achieved = ops / t_force / 1e9
     traffic = None
-    if SWEEP_TRAFFIC["bytes_per_launch"] is not None and SWEEP_TRAFFIC["src_sha"] == sweep_src_sha():
+    if (measured and SWEEP_TRAFFIC["bytes_per_launch"] is not None
+            and SWEEP_TRAFFIC["src_sha"] == sweep_src_sha()):
         traffic = SWEEP_TRAFFIC["bytes_per_launch"]
     return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_GOPS, "unit": "Gop/s",
             "frac": achieved / VALU_PEAK_GOPS, "traffic": traffic, "kernel": kernel,
@@ -238,7 +241,9 @@ def plain_measure(a, variant, boxes, steps, warmup):
         "candidates_per_particle": tot_cands / (steps * n), "search_efficiency": tot_evals / tot_cands,
         "deterministic": bool(a.deterministic) and a.sweep != "half",
         "roofline": roofline_alu(tot_cands, tot_evals, t_force, steps,
-                                 f"sweep[{a.sweep}]<{variant},{a.precision}>", n),
+                                 f"sweep[{a.sweep}]<{variant},{a.precision}>", n,
+                                 measured=(variant == "do" and a.precision == "fp32" and n == 1 << 20
+                                           and set(sched) == {"particle"})),
     }
 
 
